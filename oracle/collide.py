@@ -1,0 +1,163 @@
+"""Collision operator Q^{pq}(f^p, f^q) (oracle; test infrastructure).
+
+``collide`` follows Algorithm 2 of the paper step by step with the oracle's
+own naive DFT; ``collide_direct`` evaluates the projected operator of
+Eq. (apndx_Qprojected) as a direct O(N^6) sum over wave-index pairs, with the
+same quadrature of G^+ (Eqs. realGG, lowrank) and G^- (Eq. Gmm_vss), so the
+two can be compared at small N.  Arrays are indexed [x, y, z].
+"""
+import math
+
+import numpy as np
+
+from . import dft
+from .quadrature import gauss_legendre, sphere_set, truncation_radius, wave_grid
+from .tables import beta_reduced, gain_table, kernel_exponents, loss_table
+
+
+class PairPlan:
+    """Everything Algorithm 2 needs for one ordered pair (p, q): the inputs
+    of Algorithm 1 and its outputs b, c, plus beta.
+
+    N, L        velocity grid points per axis and half-width of D_L
+    mp, mq      species masses
+    omega,alpha VSS parameters of the pair (alpha = 1 is VHS)
+    R           truncation radius (None: the rule of Sec. 2.1)
+    Nrho        Gauss-Legendre points on [0, R]
+    sigma, w_sigma  sphere quadrature (M points, weights summing to 4 pi)
+    beta        prefactor; None => unit reduced Knudsen number (beta_reduced)
+    gamma, eta  override the kernel exponents (Krook-Wu uses gamma = eta = 0)
+    """
+
+    def __init__(self, N, L, mp, mq, omega, alpha, Nrho, sigma, w_sigma,
+                 R=None, beta=None, gamma=None, eta=None):
+        self.N, self.L, self.mp, self.mq = N, L, float(mp), float(mq)
+        g, e = kernel_exponents(omega, alpha)
+        self.gamma = g if gamma is None else gamma
+        self.eta = e if eta is None else eta
+        self.R = truncation_radius(L, mp, mq) if R is None else R
+        self.rho, self.w_rho = gauss_legendre(Nrho, self.R)
+        self.sigma = np.asarray(sigma, dtype=float)
+        self.w_sigma = np.asarray(w_sigma, dtype=float)
+        self.beta = beta_reduced(mp, mq, omega, alpha) if beta is None else beta
+        self.b = gain_table(N, L, self.rho, self.sigma, mp, mq, self.gamma, self.eta)
+        self.c = loss_table(N, L, self.rho, self.w_rho, self.gamma, self.eta)
+
+
+def phase_argument(plan, r, m):
+    """a = pi/L rho_r (l . sigma_m) on the N^3 wave grid (Algorithm 1, table a)."""
+    lx, ly, lz = wave_grid(plan.N)
+    s = plan.sigma[m]
+    return math.pi / plan.L * plan.rho[r] * (lx * s[0] + ly * s[1] + lz * s[2])
+
+
+def collide(plan, f, g):
+    """Q = beta Re(ifft(QG) - f * ifft(c * FTg)), Algorithm 2.
+
+    f = F^p and g = F^q are real N^3 arrays.  The (r, m) loop runs r outer,
+    m inner, in increasing order."""
+    mp, mq = plan.mp, plan.mq
+    FTf = dft.fft3(f)
+    FTg = dft.fft3(g)
+    QG = np.zeros_like(FTf)
+    for r in range(len(plan.rho)):
+        for m in range(len(plan.sigma)):
+            a = phase_argument(plan, r, m)
+            t1 = np.exp(1j * mq / (mp + mq) * a) * FTf
+            t2 = np.exp(-1j * mp / (mp + mq) * a) * FTg
+            t3 = dft.fft3(dft.ifft3(t1) * dft.ifft3(t2))
+            QG = QG + plan.w_rho[r] * plan.w_sigma[m] * plan.b[r, m] * t3
+    return plan.beta * np.real(dft.ifft3(QG) - f * dft.ifft3(plan.c * FTg))
+
+
+def collide_gain_loss(plan, f, g):
+    """The two parts of Algorithm 2 before they are combined:
+    (beta Re ifft(QG), beta Re(f * ifft(c FTg)))."""
+    mp, mq = plan.mp, plan.mq
+    FTf, FTg = dft.fft3(f), dft.fft3(g)
+    QG = np.zeros_like(FTf)
+    for r in range(len(plan.rho)):
+        for m in range(len(plan.sigma)):
+            a = phase_argument(plan, r, m)
+            t1 = np.exp(1j * mq / (mp + mq) * a) * FTf
+            t2 = np.exp(-1j * mp / (mp + mq) * a) * FTg
+            QG = QG + plan.w_rho[r] * plan.w_sigma[m] * plan.b[r, m] * \
+                dft.fft3(dft.ifft3(t1) * dft.ifft3(t2))
+    gain = plan.beta * np.real(dft.ifft3(QG))
+    loss = plan.beta * np.real(f * dft.ifft3(plan.c * FTg))
+    return gain, loss
+
+
+def kernel_mode_gain(plan, l, m):
+    """G^{pq+}(l, m) of Eq. (realGG) by the (rho_r, sigma_m) quadrature:
+    sum_{r,m} w_r w_m F(k, rho_r, sigma_m) exp(i pi/L rho (a_q l - a_p m).sigma)
+    with k = l + m wrapped into [-N/2, N/2) (circular convolution)."""
+    N = plan.N
+    aq = plan.mq / (plan.mp + plan.mq)
+    ap = plan.mp / (plan.mp + plan.mq)
+    l = np.asarray(l)
+    m = np.asarray(m)
+    k = (l + m + N // 2) % N - N // 2
+    kidx = tuple(k % N)  # storage index of wave k
+    out = 0.0j
+    for r in range(len(plan.rho)):
+        for s in range(len(plan.sigma)):
+            sg = plan.sigma[s]
+            ph = math.pi / plan.L * plan.rho[r] * float(np.dot(aq * l - ap * m, sg))
+            out += plan.w_rho[r] * plan.w_sigma[s] * plan.b[(r, s) + kidx] * np.exp(1j * ph)
+    return out
+
+
+def collide_direct(plan, f, g):
+    """Direct O(N^6) evaluation of Eq. (apndx_Qprojected) on the discrete
+    Fourier coefficients: Qhat_k = sum_{l+m = k mod N} [G+(l,m) - G-(m)]
+    fhat_l ghat_m, fhat = fft3(f)/N^3, then Q = beta Re(sum_k Qhat_k e^{...}).
+    Vectorised over l for each m.  Only sensible for N <= 8."""
+    N = plan.N
+    n3 = N ** 3
+    fh = dft.fft3(f) / n3
+    gh = dft.fft3(g) / n3
+    aq = plan.mq / (plan.mp + plan.mq)
+    ap = plan.mp / (plan.mp + plan.mq)
+    lx, ly, lz = wave_grid(N)
+    L3 = np.stack([lx.ravel(), ly.ravel(), lz.ravel()], axis=1)  # storage order
+    fh = fh.ravel()
+    gh = gh.ravel()
+    c = plan.c.ravel()
+    b = plan.b.reshape(len(plan.rho), len(plan.sigma), n3)
+    Qh = np.zeros(n3, dtype=complex)
+    for mi in range(n3):
+        mvec = L3[mi]
+        kvec = (L3 + mvec + N // 2) % N - N // 2
+        kidx = ((kvec[:, 0] % N) * N + (kvec[:, 1] % N)) * N + (kvec[:, 2] % N)
+        Gp = np.zeros(n3, dtype=complex)
+        for r in range(len(plan.rho)):
+            for s in range(len(plan.sigma)):
+                sg = plan.sigma[s]
+                ph = math.pi / plan.L * plan.rho[r] * ((aq * L3 - ap * mvec) @ sg)
+                Gp += plan.w_rho[r] * plan.w_sigma[s] * b[r, s, kidx] * np.exp(1j * ph)
+        contrib = (Gp - c[mi]) * fh * gh[mi]
+        np.add.at(Qh, kidx, contrib)
+    Q = dft.ifft3(Qh.reshape(N, N, N)) * n3
+    return plan.beta * np.real(Q)
+
+
+def default_pair_plan(N, L, masses, p, q, omega, alpha, Nrho, sphere, M=None,
+                      R=None, beta=None, gamma=None, eta=None):
+    """Convenience: PairPlan for species (p, q) with a named sphere set."""
+    sigma, w = sphere_set(sphere, M)
+    return PairPlan(N, L, masses[p], masses[q], omega, alpha, Nrho, sigma, w,
+                    R=R, beta=beta, gamma=gamma, eta=eta)
+
+
+def mixture_collision(pair_plans, F):
+    """sum_q Q^{pq}(f^p, f^q) for every node and species p of
+    F [nodes, ns, N, N, N]; pair_plans[p][q] is the PairPlan of (p, q)
+    (Eq. bzeNonDim, with 1/Kn inside beta)."""
+    out = np.zeros_like(F)
+    ns = F.shape[1]
+    for i in range(F.shape[0]):
+        for p in range(ns):
+            for q in range(ns):
+                out[i, p] += collide(pair_plans[p][q], F[i, p], F[i, q])
+    return out

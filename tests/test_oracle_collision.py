@@ -1,0 +1,175 @@
+"""Pins of the oracle's collision operator (Algorithm 2) against the direct
+Galerkin sum, the Krook-Wu exact solution (Table 1) and the invariants of
+the Boltzmann collision operator."""
+import math
+import os
+
+import numpy as np
+import pytest
+
+from oracle import conservation as cons
+from oracle.collide import PairPlan, collide, collide_direct, collide_gain_loss, kernel_mode_gain
+from oracle.krook_wu import KrookWu
+from oracle.quadrature import sphere_set, velocity_grid
+from oracle.tables import sinc
+from paper_1903_04670_amd import workloads as wl
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.mark.parametrize("N,alpha,sphere", [(4, 1.0, "icosahedron"), (6, 1.0, "octahedron"),
+                                            (4, 1.4, "icosahedron"), (6, 1.4, "fibonacci")])
+def test_algorithm2_equals_direct_galerkin_sum(N, alpha, sphere):
+    rng = np.random.default_rng(N)
+    s, w = sphere_set(sphere, 7 if sphere == "fibonacci" else None)
+    pl = PairPlan(N, 5.0, 1.0, 2.5, 0.7, alpha, 3, s, w, R=4.0)
+    f, g = rng.random((N, N, N)), rng.random((N, N, N))
+    Q1, Q2 = collide(pl, f, g), collide_direct(pl, f, g)
+    assert np.max(np.abs(Q1 - Q2)) <= 1e-13 * np.max(np.abs(Q1))
+
+
+def test_kernel_mode_matches_continuous_vhs():
+    """Eq. (realGG) for VHS reduces to a 1-D integral:
+    G+(l,m) = int_0^R rho^{gamma+2} (4 pi)^2 sinc(pi/L rho a_q |l+m|)
+              sinc(pi/L rho |a_q l - a_p m|) d rho.
+    The (rho_r, sigma_m) quadrature converges to it."""
+    N, L, mp, mq, R = 8, 5.0, 1.0, 3.0, 4.0
+    aq, ap = mq / (mp + mq), mp / (mp + mq)
+    l, m = np.array([1, 0, -1]), np.array([0, 2, 1])
+    k = l + m
+    rr = np.linspace(0, R, 20001)
+    integrand = rr ** 3 * (4 * math.pi) ** 2 * sinc(math.pi / L * rr * aq * np.linalg.norm(k)) * \
+        sinc(math.pi / L * rr * np.linalg.norm(aq * l - ap * m))
+    ref = np.trapezoid(integrand, rr)
+    s, w = sphere_set("fibonacci", 1500)
+    pl = PairPlan(N, L, mp, mq, 0.5, 1.0, 24, s, w, R=R)
+    got = kernel_mode_gain(pl, l, m)
+    assert abs(got - ref) < 2e-4 * abs(ref)
+    assert abs(got.imag) < 1e-3 * abs(ref)
+
+
+def test_krook_wu_derivative_formula_by_finite_difference():
+    for ratio in (1.0, 4.0):
+        kw = KrookWu(1.0, ratio)
+        assert abs(kw.constraint()) < 1e-14
+        v2 = np.linspace(0, 30, 61)
+        for p in (1, 2):
+            for t in (5.5, 8.0):
+                e = 1e-5
+                fd = (kw.f(p, t + e, v2) - kw.f(p, t - e, v2)) / (2 * e)
+                assert np.max(np.abs(fd - kw.dfdt(p, t, v2))) < 1e-9
+
+
+def test_krook_wu_density_is_conserved():
+    for ratio in (1.0, 4.0):
+        kw = KrookWu(1.0, ratio)
+        c, h = velocity_grid(64, 12.0)
+        cx, cy, cz = np.meshgrid(c, c, c, indexing="ij")
+        v2 = cx ** 2 + cy ** 2 + cz ** 2
+        for p in (1, 2):
+            for t in (5.5, 10.0):
+                assert abs(np.sum(kw.f(p, t, v2)) * h ** 3 - 1.0) < 1e-10
+                assert abs(np.sum(kw.dfdt(p, t, v2)) * h ** 3) < 1e-9
+
+
+def _table1_rows():
+    rows = []
+    with open(os.path.join(GOLDEN, "table1_krook_wu.txt")) as fh:
+        for line in fh:
+            if line.startswith("#") or not line.strip():
+                continue
+            N, Nr, M, ratio, e1, e2 = line.split()
+            rows.append((int(N), int(Nr), int(M), float(ratio), float(e1),
+                         None if e2 == "-" else float(e2)))
+    return rows
+
+
+def krook_wu_errors(N, Nr, M, ratio, t=5.5, L=12.0):
+    kw = KrookWu(1.0, ratio)
+    c, h = velocity_grid(N, L)
+    cx, cy, cz = np.meshgrid(c, c, c, indexing="ij")
+    v2 = cx ** 2 + cy ** 2 + cz ** 2
+    f = {p: kw.f(p, t, v2) for p in (1, 2)}
+    s, w = sphere_set("octahedron" if M == 6 else "icosahedron")
+    masses = {1: 1.0, 2: ratio}
+    errs = []
+    for p in (1, 2):
+        tot = 0.0
+        for q in (1, 2):
+            pl = PairPlan(N, L, masses[p], masses[q], 1.0, 1.0, Nr, s, w,
+                          beta=kw.beta(p, q), gamma=0.0, eta=0.0)
+            tot = tot + collide(pl, f[p], f[q])
+        errs.append(np.max(np.abs(tot - kw.dfdt(p, t, v2))))
+    return errs
+
+
+@pytest.mark.parametrize("row", _table1_rows(), ids=lambda r: "N%d_Nr%d_M%d_r%g" % r[:4])
+def test_table1_krook_wu_errors(row):
+    """The oracle reproduces Table 1's printed errors within a factor 1.5."""
+    N, Nr, M, ratio, e1, e2 = row
+    got = krook_wu_errors(N, Nr, M, ratio)
+    assert e1 / 1.5 <= got[0] <= 1.5 * e1, got
+    if e2 is not None:
+        assert e2 / 1.5 <= got[1] <= 1.5 * e2, got
+
+
+def _maxwell_pair(N, S, mp, mq, u, T, omega=0.5):
+    L, R = wl.box_for_support(S)
+    s, w = sphere_set("icosahedron")
+    pl = PairPlan(N, L, mp, mq, omega, 1.0, N // 2, s, w, R=R)
+    return pl, wl.maxwellian(N, L, mp, 1.0, u, T), wl.maxwellian(N, L, mq, 0.7, u, T), L
+
+
+def test_equilibrium_residual_decays_with_N():
+    """Q(M_p, M_q) -> 0 for Maxwellians at a common bulk velocity and
+    temperature; spectral accuracy, so the residual must fall with N."""
+    res = []
+    for N in (16, 24, 32):
+        pl, fp, fq, _ = _maxwell_pair(N, 4.0, 1.0, 2.0, (0.3, -0.2, 0.1), 1.0)
+        gain, loss = collide_gain_loss(pl, fp, fq)
+        res.append(np.max(np.abs(gain - loss)) / np.max(np.abs(loss)))
+    assert res[-1] < 5e-3
+    assert all(a > b for a, b in zip(res, res[1:])), res
+
+
+def test_conservation_decays_with_N():
+    """Mass of Q^{pq} per species and total momentum and energy of
+    (Q^{pq}, Q^{qp}): residuals fall with N (non-equilibrium inputs)."""
+    out = []
+    for N in (16, 24, 32):
+        S = 4.0
+        L, R = wl.box_for_support(S)
+        mp, mq = 1.0, 2.0
+        s, w = sphere_set("icosahedron")
+        fp = wl.maxwellian(N, L, mp, 1.0, (0.5, 0, 0), 1.0) + wl.maxwellian(N, L, mp, 0.5, (-0.5, 0.2, 0), 0.8)
+        fq = wl.maxwellian(N, L, mq, 0.8, (0, 0.3, 0), 1.2)
+        Qpq = collide(PairPlan(N, L, mp, mq, 0.6, 1.0, N // 2, s, w, R=R), fp, fq)
+        Qqp = collide(PairPlan(N, L, mq, mp, 0.6, 1.0, N // 2, s, w, R=R), fq, fp)
+        mom = cons.moments(np.stack([Qpq, Qqp]), N, L, [mp, mq])
+        scale = np.max(np.abs(cons.moments(np.stack([np.abs(Qpq), np.abs(Qqp)]), N, L, [mp, mq])))
+        out.append(np.max(np.abs(mom)) / scale)
+    assert out[-1] < 3e-3
+    assert out[0] > out[1] > out[-1] and out[0] > 5 * out[-1], out
+
+
+def test_beta_reduced_is_symmetric_and_matches_kn_form():
+    from oracle.tables import beta_prefactor, beta_reduced
+    for mp, mq, om, al in [(1.0, 2.0, 0.6, 1.0), (1.0, 4.0, 0.7, 1.4)]:
+        assert abs(beta_reduced(mp, mq, om, al) - beta_reduced(mq, mp, om, al)) < 1e-16
+        kn = 1.0 / math.sqrt(1.0 + mp / mq)
+        assert abs(beta_prefactor(mp, mq, om, al, kn) - beta_reduced(mp, mq, om, al)) < 1e-15
+
+
+def test_projection_restores_invariants():
+    rng = np.random.default_rng(11)
+    N, L = 8, 6.0
+    masses = [1.0, 2.0, 4.0]
+    Q = rng.standard_normal((3, N, N, N))
+    Qt = cons.project(Q, N, L, masses)
+    m0 = cons.moments(np.abs(Q), N, L, masses)
+    assert np.max(np.abs(cons.moments(Qt, N, L, masses)) / np.abs(m0)) < 1e-13
+    # idempotent, and the change lies in the row space of C (orthogonal to
+    # anything with zero moments)
+    assert np.max(np.abs(cons.project(Qt, N, L, masses) - Qt)) < 1e-13 * np.max(np.abs(Q))
+    Z = cons.project(rng.standard_normal((3, N, N, N)), N, L, masses)
+    assert abs(np.sum((Q - Qt) * Z)) < 1e-10 * np.sqrt(np.sum(Q ** 2) * np.sum(Z ** 2))
