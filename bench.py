@@ -1,0 +1,198 @@
+"""Throughput of the fast spectral collision hot path on one MI355X.
+
+python bench.py [--gpus 1] [--steps K] [--warmup W]
+
+Workload: the two-species 1-D-x Couette problem (masses 1 and 2, VHS omega
+0.5/0.6/0.7, N = 32^3 velocity grid, S = 4, R = 8, icosahedron M = 12,
+N_rho = 16, K = 16 DG elements of order P = 3, i.e. 64 spatial nodes,
+diffuse walls at +-0.5, seeded 1% noise on unit Maxwellians).  One step is
+one SSP-RK3 step (dt = 1e-3): three right-hand sides, each the DG transport
+plus all 64 x 4 ordered-pair collision evaluations.  The metric is
+collision evaluations per second (768 per step).  The plain FP64 path is
+`value`; the FP32-mixed path with the FP64 conservation projection is
+reported beside it.  Inputs are resident in HBM before timing starts.
+
+Prints one JSON line (rank 0).
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, HERE)
+
+HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6
+FP32_PEAK_TFLOPS = 157.3
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    return ap.parse_args()
+
+
+def gain_yz_model(N, M, Nr, Sx, elt):
+    """Algorithmic bytes and flops of k_gain_yz per collision evaluation.
+
+    Per (eval, r): reads the 2*Sx distinct shifted arrays X (N^3 complex
+    each) and writes one array C_r.  Flops (5 n log2 n per complex length-n
+    transform): for each of M directions two inverse 2-D transforms of every
+    x-plane, two phase multiplies (6 flops/point each), the complex product
+    and weighted accumulation (8 flops/point); one forward 2-D transform of
+    the sum."""
+    n3 = N ** 3
+    sc = 2 * elt
+    bytes_ = Nr * (2 * Sx + 1) * n3 * sc
+    t2 = 5.0 * N * N * np.log2(N * N)  # per plane
+    flops = Nr * N * (2 * M * t2 + M * (2 * 6 + 8) * N * N + t2)
+    return bytes_, flops
+
+
+def run(args):
+    import torch
+    from paper_1903_04670_amd import dgfs, workloads as wl
+
+    cfg = wl.couette_two_species()
+    dev = torch.device("cuda:0")
+    F0 = torch.from_numpy(cfg["F"]).to(dev)
+    mesh = dgfs.make_mesh(cfg["K"], u_left=cfg["u_left"], u_right=cfg["u_right"])
+    n_nodes = F0.shape[0]
+    evals_per_step = 3 * n_nodes * cfg["ns"] ** 2
+    out = {}
+    for prec in ("fp64", "fp32"):
+        plan = dgfs.Plan(cfg["masses"], cfg["omega"], cfg["alpha"], cfg["N"], cfg["L"], cfg["Nrho"],
+                         sphere=cfg["sphere"], M=cfg["M"], S=cfg["S"], R=cfg["R"], dg_order=cfg["P"],
+                         precision=prec)
+        project = prec == "fp32"
+        F = F0.clone()
+        ws = dgfs.workspace(plan, n_nodes, dgfs.OP_STEP, dev)
+        stream = torch.cuda.current_stream()
+        for _ in range(args.warmup):
+            dgfs.step(plan, F, cfg["dt"], 1, mesh=mesh, project=project, ws=ws)
+        torch.cuda.synchronize()
+        # timed region: per-kernel HIP events on the library's launch stream
+        dgfs.profile_enable(True)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        e0.record(stream)
+        for _ in range(args.steps):
+            dgfs.step(plan, F, cfg["dt"], 1, mesh=mesh, project=project, ws=ws)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        kern = dgfs.profile_read()
+        dgfs.profile_enable(False)
+        gpu_ms = e0.elapsed_time(e1)
+        ms = max(wall * 1e3, gpu_ms) / args.steps
+        finite = bool(torch.isfinite(F).all())
+        # graph-replay throughput (the production path) without kernel events
+        for _ in range(args.warmup):
+            dgfs.step(plan, F, cfg["dt"], 1, mesh=mesh, project=project, ws=ws)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        dgfs.step(plan, F, cfg["dt"], args.steps, mesh=mesh, project=project, ws=ws)
+        torch.cuda.synchronize()
+        ms_graph = (time.perf_counter() - t0) * 1e3 / args.steps
+        out[prec] = dict(ms=ms, ms_graph=ms_graph, kern=kern, finite=finite, plan=plan,
+                         Sx=plan_sx(plan))
+    return cfg, evals_per_step, out
+
+
+def plan_sx(plan):
+    # distinct x components of the sphere set (the library shares x transforms across them)
+    return len(np.unique(np.round(plan.sigma[:, 0], 15)))
+
+
+def cpu_baseline(seconds):
+    """The oracle (as it stands) on the host: one ordered-pair evaluation at
+    a time on the same N = 32 workload until about `seconds` have passed."""
+    from threadpoolctl import threadpool_info
+    from oracle.collide import PairPlan, collide
+    from oracle.quadrature import sphere_set
+    from paper_1903_04670_amd import workloads as wl
+    cfg = wl.couette_two_species(K=1, P=1)
+    s, w = sphere_set(cfg["sphere"], cfg["M"])
+    plans = {(p, q): PairPlan(cfg["N"], cfg["L"], cfg["masses"][p], cfg["masses"][q], cfg["omega"][p][q],
+                              cfg["alpha"][p][q], cfg["Nrho"], s, w, R=cfg["R"][p][q])
+             for p in range(2) for q in range(2)}
+    n = 0
+    t0 = time.perf_counter()
+    pairs = list(plans)
+    while True:
+        node = n // 4 % cfg["F"].shape[0]
+        p, q = pairs[n % 4]
+        collide(plans[p, q], cfg["F"][node, p], cfg["F"][node, q])
+        n += 1
+        if time.perf_counter() - t0 > seconds and n >= 4:
+            break
+    dt = time.perf_counter() - t0
+    threads = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
+    return dict(value=n / dt, unit="collision evals/s", cores=int(threads), kind="oracle",
+                sample="%d ordered-pair evaluations (N=32, M=12, N_rho=16) of the Couette workload, %.1f s"
+                       % (n, dt))
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: the collision hot path is benchmarked on a single "
+              "MI355X (multi-GPU sharding is a design note, not part of this build).", file=sys.stderr)
+        sys.exit(2)
+    cfg, evals_per_step, res = run(args)
+    r64, r32 = res["fp64"], res["fp32"]
+    value = evals_per_step / (r64["ms"] / 1e3)
+    # dominant kernel roofline (FP64 path)
+    name = "k_gain_yz"
+    cnt, tot = r64["kern"].get(name, (0, 0.0))
+    avg_ms = tot / max(cnt, 1)
+    launches_per_step = cnt / args.steps
+    evals_per_launch = evals_per_step / max(launches_per_step, 1)
+    b, f = gain_yz_model(cfg["N"], cfg["M"], cfg["Nrho"], r64["Sx"], 8)
+    achieved_gbs = b * evals_per_launch / (avg_ms / 1e3) / 1e9
+    achieved_tf = f * evals_per_launch / (avg_ms / 1e3) / 1e12
+    roof = {"bound": "hbm", "achieved": round(achieved_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved_gbs / HBM_PEAK_GBS, 4), "traffic": None,
+            "kernel": name, "avg_launch_ms": round(avg_ms, 4), "evals_per_launch": evals_per_launch,
+            "fp64_tflops": round(achieved_tf, 2), "fp64_flop_frac": round(achieved_tf / FP64_PEAK_TFLOPS, 4)}
+    line = {
+        "metric": "collision evals/s at N=32^3 (FP64; FP32-mixed beside it)",
+        "value": round(value, 1),
+        "unit": "collision evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(r64["ms"], 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "couette 2 species N=32 M=12 Nrho=16 K=16 P=3 (64 nodes), SSP-RK3 step",
+                   "evals_per_step": evals_per_step, "nodes": 64, "pairs": 4},
+        "fp32_mixed": {"value": round(evals_per_step / (r32["ms"] / 1e3), 1), "ms_per_step": round(r32["ms"], 3),
+                       "projection": "fp64", "dtype": "f32 transforms, f64 moments/projection"},
+        "graph_replay": {"fp64_evals_per_s": round(evals_per_step / (r64["ms_graph"] / 1e3), 1),
+                         "fp32_mixed_evals_per_s": round(evals_per_step / (r32["ms_graph"] / 1e3), 1)},
+        "kernels_ms_per_step": {k: round(v[1] / args.steps, 4) for k, v in sorted(r64["kern"].items())},
+        "kernels_ms_per_step_fp32": {k: round(v[1] / args.steps, 4) for k, v in sorted(r32["kern"].items())},
+        "roofline": roof,
+        "finite": r64["finite"] and r32["finite"],
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,167 @@
+// Launch layer of the collision pipeline and the dgfs_collide entry point.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdlib>
+#include <cstring>
+
+#include "collide_kernels.hpp"
+#include "pipeline.hpp"
+#include "launch.hpp"
+
+namespace dgfs {
+
+template <int N> constexpr int groups_for() { return N >= 64 ? 1 : (64 / N > 0 ? 64 / N : 1); }
+
+template <typename T, int N>
+static hipError_t launch_pipeline_N(const PipeArgs &a, const FwdArgs &fw, const FinalArgs &fa, hipStream_t st,
+                                    bool do_fwd) {
+  constexpr int G = groups_for<N>();
+  const int E = a.n_nodes * a.n_pairs;
+  if (do_fwd) {
+    const int planes = N * fw.n_nodes * fw.nz;
+    DGFS_LAUNCH("k_fwd_yz", (k_fwd_yz<T, N, G>), dim3((planes + G - 1) / G), dim3(G * N), 0, st, fw);
+  }
+  const int pb = (N * N + 63) / 64;
+  DGFS_LAUNCH("k_shift_x", (k_shift_x<T, N>), dim3(pb, 2, E), dim3(64), 0, st, a);
+  DGFS_LAUNCH("k_gain_yz", (k_gain_yz<T, N, G>), dim3(N, a.Nr, E), dim3(G * N), 0, st, a);
+  DGFS_LAUNCH("k_gain_x", (k_gain_x<T, N>), dim3(pb, E), dim3(64), 0, st, a);
+  const int fplanes = N * a.n_nodes * fa.n_out;
+  DGFS_LAUNCH("k_final_yz", (k_final_yz<T, N, G>), dim3((fplanes + G - 1) / G), dim3(G * N), 0, st, a, fa);
+  return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t launch_pipeline_T(int N, const PipeArgs &a, const FwdArgs &fw, const FinalArgs &fa,
+                                    hipStream_t st, bool do_fwd) {
+  switch (N) {
+    case 4: return launch_pipeline_N<T, 4>(a, fw, fa, st, do_fwd);
+    case 6: return launch_pipeline_N<T, 6>(a, fw, fa, st, do_fwd);
+    case 8: return launch_pipeline_N<T, 8>(a, fw, fa, st, do_fwd);
+    case 12: return launch_pipeline_N<T, 12>(a, fw, fa, st, do_fwd);
+    case 16: return launch_pipeline_N<T, 16>(a, fw, fa, st, do_fwd);
+    case 18: return launch_pipeline_N<T, 18>(a, fw, fa, st, do_fwd);
+    case 24: return launch_pipeline_N<T, 24>(a, fw, fa, st, do_fwd);
+    case 32: return launch_pipeline_N<T, 32>(a, fw, fa, st, do_fwd);
+    case 36: return launch_pipeline_N<T, 36>(a, fw, fa, st, do_fwd);
+    case 48: return launch_pipeline_N<T, 48>(a, fw, fa, st, do_fwd);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_pipeline(const dgfs_plan_s *pl, const PipeArgs &a, const FwdArgs &fw, const FinalArgs &fa,
+                           hipStream_t st, bool do_fwd) {
+  if (pl->precision == DGFS_FP64) return launch_pipeline_T<double>(pl->N, a, fw, fa, st, do_fwd);
+  return launch_pipeline_T<float>(pl->N, a, fw, fa, st, do_fwd);
+}
+
+static size_t align256(size_t b) { return (b + 255) / 256 * 256; }
+
+int max_evals_per_chunk() {
+  static int v = [] {
+    const char *s = std::getenv("DGFS_CHUNK_EVALS");
+    int x = s ? std::atoi(s) : 64;
+    return x > 0 ? x : 64;
+  }();
+  return v;
+}
+
+int chunk_nodes(const dgfs_plan_s *pl, int64_t n_nodes, int n_pairs) {
+  int64_t b = std::max<int64_t>(1, max_evals_per_chunk() / n_pairs);
+  return (int)std::max<int64_t>(1, std::min<int64_t>(b, n_nodes));
+}
+
+size_t pipeline_bytes(const dgfs_plan_s *pl, int B, int n_pairs, int nz) {
+  const size_t n3 = (size_t)pl->N * pl->N * pl->N, c = 2 * pl->elt();
+  const size_t E = (size_t)B * n_pairs;
+  return align256((size_t)B * nz * n3 * c) + align256(E * 2 * pl->Nr * pl->Sx * n3 * c) +
+         align256(E * pl->Nr * n3 * c) + align256(E * 2 * n3 * c);
+}
+
+void pipeline_carve(const dgfs_plan_s *pl, int B, int n_pairs, int nz, void *ws, PipeArgs &a) {
+  const size_t n3 = (size_t)pl->N * pl->N * pl->N, c = 2 * pl->elt();
+  const size_t E = (size_t)B * n_pairs;
+  char *p = static_cast<char *>(ws);
+  a.Z = p;
+  p += align256((size_t)B * nz * n3 * c);
+  a.X = p;
+  p += align256(E * 2 * pl->Nr * pl->Sx * n3 * c);
+  a.Cb = p;
+  p += align256(E * pl->Nr * n3 * c);
+  a.V = p;
+}
+
+void pipeline_common(const dgfs_plan_s *pl, PipeArgs &a) {
+  a.Nr = pl->Nr;
+  a.Sx = pl->Sx;
+  a.M = pl->M;
+  a.ns = pl->ns;
+  a.pairs = pl->pair_dev;
+  a.wm = pl->wm_dev;
+  a.sidx = pl->sidx_dev;
+}
+
+}  // namespace dgfs
+
+using namespace dgfs;
+
+extern "C" dgfs_status dgfs_collide(dgfs_plan pl, int64_t n_nodes, int32_t p, int32_t q, const double *fp,
+                                    const double *fq, int64_t node_stride, double *Q, int64_t out_stride,
+                                    uint32_t flags, void *ws, size_t ws_bytes, void *stream) {
+  if (!pl) { set_error("dgfs_collide: NULL plan"); return DGFS_EINVAL; }
+  if (n_nodes < 0) { set_error("dgfs_collide: n_nodes < 0"); return DGFS_EINVAL; }
+  if (p < 0 || q < 0 || p >= pl->ns || q >= pl->ns) { set_error("dgfs_collide: species (%d, %d) out of range", p, q); return DGFS_EINVAL; }
+  if (flags & ~(DGFS_ACCUMULATE | DGFS_CHECK)) { set_error("dgfs_collide: unsupported flags 0x%x", flags); return DGFS_EINVAL; }
+  if (n_nodes == 0) return DGFS_OK;
+  if (!fp || !fq || !Q) { set_error("dgfs_collide: NULL array"); return DGFS_EINVAL; }
+  const int64_t n3 = (int64_t)pl->N * pl->N * pl->N;
+  if (n_nodes > 1 && (node_stride < n3 || out_stride < n3)) { set_error("dgfs_collide: strides must be >= N^3"); return DGFS_EINVAL; }
+  const int nz = (p == q && fp == fq) ? 1 : 2;
+  const int B = chunk_nodes(pl, n_nodes, 1);
+  const size_t need = pipeline_bytes(pl, B, 1, nz);
+  if (!ws || ws_bytes < need) { set_error("dgfs_collide: workspace %zu bytes, need %zu", ws_bytes, need); return DGFS_EWORKSPACE; }
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  PipeArgs a{};
+  pipeline_common(pl, a);
+  pipeline_carve(pl, B, 1, nz, ws, a);
+  a.n_pairs = 1;
+  a.nz = nz;
+  a.pair_id[0] = p * pl->ns + q;
+  a.zp[0] = 0;
+  a.zq[0] = nz == 1 ? 0 : 1;
+  for (int64_t n0 = 0; n0 < n_nodes; n0 += B) {
+    const int nb = (int)std::min<int64_t>(B, n_nodes - n0);
+    a.n_nodes = nb;
+    FwdArgs fw{};
+    fw.src[0] = fp + n0 * node_stride;
+    fw.src[1] = fq + n0 * node_stride;
+    fw.node_stride = node_stride;
+    fw.n_nodes = nb;
+    fw.nz = nz;
+    fw.Z = a.Z;
+    FinalArgs fa{};
+    fa.n_out = 1;
+    fa.qcount = 1;
+    fa.fsrc[0] = fp + n0 * node_stride;
+    fa.f_stride = node_stride;
+    fa.out[0] = Q + n0 * out_stride;
+    fa.out_stride = out_stride;
+    fa.accumulate = (flags & DGFS_ACCUMULATE) ? 1 : 0;
+    hipError_t e = launch_pipeline(pl, a, fw, fa, st, true);
+    if (e != hipSuccess) return hip_status(e, "dgfs_collide launch");
+  }
+  if (flags & DGFS_CHECK) return check_finite(Q, n_nodes, n3, out_stride, st);
+  return DGFS_OK;
+}
+
+extern "C" size_t dgfs_workspace_bytes(dgfs_plan pl, int64_t n_nodes, int32_t op) {
+  if (!pl || n_nodes <= 0) return 0;
+  switch (op) {
+    case DGFS_OP_COLLIDE: {
+      const int B = chunk_nodes(pl, n_nodes, 1);
+      return pipeline_bytes(pl, B, 1, 2);
+    }
+    default:
+      return extra_workspace_bytes(pl, n_nodes, op);
+  }
+}

@@ -1,0 +1,65 @@
+// Internal types of libdgfs shared by the host plan builder and the kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/dgfs.h"
+
+namespace dgfs {
+
+constexpr int kMaxPairs = DGFS_MAX_SPECIES * DGFS_MAX_SPECIES;
+
+// Per ordered pair (p, q): device tables, in the plan's compute type T
+// (double for DGFS_FP64, float for DGFS_FP32_MIXED).  Complex = (re, im).
+struct PairDev {
+  const void *px;    // [2][Nr][S][N] cplx: side 0 e^{+i th_q s v}/N^3, side 1 e^{-i th_p s v}/N^3
+  const void *pyz;   // [2][Nr][M][2][N] cplx: side 0 e^{+i th_q sigma_a v}, side 1 e^{-i th_p sigma_a v}; a = y, z
+  const void *gtab;  // VHS: [Nr][K2] real  w_r b_r(|k|)/N^3, indexed by |k|^2
+  const void *ctab;  // [K2] real  c(|k|)/N^3
+  double beta;
+};
+
+// Host-side parameters of one ordered pair.
+struct PairHost {
+  double mp, mq, omega, alpha, gamma, eta, beta, R;
+  std::vector<double> rho, wrho;
+};
+
+}  // namespace dgfs
+
+struct dgfs_plan_s {
+  int ns = 0, N = 0, M = 0, Nr = 0, P = 0, precision = 0;
+  double L = 0, S = 0;
+  std::vector<double> mass, sigma, wsig;
+  // grouping of the sphere directions by their x component
+  int Sx = 0;
+  std::vector<double> sx_val;  // [Sx]
+  std::vector<int> sx_idx;     // [M]
+  std::vector<dgfs::PairHost> pairs;  // [ns*ns], p-major
+  bool vhs = true;
+  // device memory owned by the plan
+  void *dev = nullptr;
+  size_t dev_bytes = 0;
+  dgfs::PairDev *pair_dev = nullptr;   // device array [ns*ns]
+  std::vector<dgfs::PairDev> pair_host;  // same pointers, host copy
+  const void *wm_dev = nullptr;        // [M] T sphere weights
+  const int *sidx_dev = nullptr;       // [M]
+  // nodal DG operators on P+1 Gauss-Lobatto points (row-major (P+1)^2)
+  std::vector<double> dg_r, dg_Dr, dg_Minv;
+  // (C C^T)^{-1} of the conservation constraints of all species (ns+4)^2
+  std::vector<double> proj_ginv;
+  // graph cache of dgfs_step (guarded by graph_mu)
+  void *graph_cache = nullptr;
+  // host copies for dgfs_plan_table
+  std::vector<std::vector<double>> ctab_host;  // [pair][K2] (c, unscaled)
+  int K2() const { return 3 * (N / 2) * (N / 2) + 1; }
+  size_t elt() const { return precision == DGFS_FP64 ? sizeof(double) : sizeof(float); }
+};
+
+namespace dgfs {
+void set_error(const char *fmt, ...);
+dgfs_status hip_status(hipError_t e, const char *what);
+}  // namespace dgfs
