@@ -6,16 +6,19 @@
 #include <cstring>
 
 #include "collide_kernels.hpp"
+#include "vss_kernels.hpp"
 #include "pipeline.hpp"
 #include "launch.hpp"
 
 namespace dgfs {
 
 template <int N> constexpr int groups_for() { return N >= 64 ? 1 : (64 / N > 0 ? 64 / N : 1); }
+// groups of 2N threads per k_gain_yz block: at least 128 threads per block
+template <int N> constexpr int gain_groups() { return 128 / (2 * N) > 0 ? 128 / (2 * N) : 1; }
 
 template <typename T, int N>
 static hipError_t launch_pipeline_N(const PipeArgs &a, const FwdArgs &fw, const FinalArgs &fa, hipStream_t st,
-                                    bool do_fwd) {
+                                    bool do_fwd, bool vss) {
   constexpr int G = groups_for<N>();
   const int E = a.n_nodes * a.n_pairs;
   if (do_fwd) {
@@ -23,9 +26,18 @@ static hipError_t launch_pipeline_N(const PipeArgs &a, const FwdArgs &fw, const 
     DGFS_LAUNCH("k_fwd_yz", (k_fwd_yz<T, N, G>), dim3((planes + G - 1) / G), dim3(G * N), 0, st, fw);
   }
   const int pb = (N * N + 63) / 64;
-  DGFS_LAUNCH("k_shift_x", (k_shift_x<T, N>), dim3(pb, 2, E), dim3(64), 0, st, a);
-  DGFS_LAUNCH("k_gain_yz", (k_gain_yz<T, N, G>), dim3(N, a.Nr, E), dim3(G * N), 0, st, a);
-  DGFS_LAUNCH("k_gain_x", (k_gain_x<T, N>), dim3(pb, E), dim3(64), 0, st, a);
+  const int pb2 = (N * N + 31) / 32;  // lane pairs: 32 x-lines per 64-thread block
+  DGFS_LAUNCH("k_shift_x", (k_shift_x<T, N>), dim3(pb2, 2, E), dim3(64), 0, st, a);
+  constexpr int GG = gain_groups<N>();
+  if (!vss) {
+    DGFS_LAUNCH("k_gain_yz", (k_gain_yz<T, N, GG>), dim3(N, a.Nr, E), dim3(GG * 2 * N), 0, st, a);
+    DGFS_LAUNCH("k_gain_x", (k_gain_x<T, N>), dim3(pb2, E), dim3(64), 0, st, a);
+  } else {
+    constexpr int TE = N >= 48 ? 1 : 2;
+    const int egroups = a.n_pairs * ((a.n_nodes + TE - 1) / TE);
+    DGFS_LAUNCH("k_gain_yz_vss", (k_gain_yz_vss<T, N, GG>), dim3(N, a.Nr, E), dim3(GG * 2 * N), 0, st, a);
+    DGFS_LAUNCH("k_gain_x_vss", (k_gain_x_vss<T, N, TE>), dim3(pb2, egroups), dim3(64), 0, st, a);
+  }
   const int fplanes = N * a.n_nodes * fa.n_out;
   DGFS_LAUNCH("k_final_yz", (k_final_yz<T, N, G>), dim3((fplanes + G - 1) / G), dim3(G * N), 0, st, a, fa);
   return hipGetLastError();
@@ -33,26 +45,26 @@ static hipError_t launch_pipeline_N(const PipeArgs &a, const FwdArgs &fw, const 
 
 template <typename T>
 static hipError_t launch_pipeline_T(int N, const PipeArgs &a, const FwdArgs &fw, const FinalArgs &fa,
-                                    hipStream_t st, bool do_fwd) {
+                                    hipStream_t st, bool do_fwd, bool vss) {
   switch (N) {
-    case 4: return launch_pipeline_N<T, 4>(a, fw, fa, st, do_fwd);
-    case 6: return launch_pipeline_N<T, 6>(a, fw, fa, st, do_fwd);
-    case 8: return launch_pipeline_N<T, 8>(a, fw, fa, st, do_fwd);
-    case 12: return launch_pipeline_N<T, 12>(a, fw, fa, st, do_fwd);
-    case 16: return launch_pipeline_N<T, 16>(a, fw, fa, st, do_fwd);
-    case 18: return launch_pipeline_N<T, 18>(a, fw, fa, st, do_fwd);
-    case 24: return launch_pipeline_N<T, 24>(a, fw, fa, st, do_fwd);
-    case 32: return launch_pipeline_N<T, 32>(a, fw, fa, st, do_fwd);
-    case 36: return launch_pipeline_N<T, 36>(a, fw, fa, st, do_fwd);
-    case 48: return launch_pipeline_N<T, 48>(a, fw, fa, st, do_fwd);
+    case 4: return launch_pipeline_N<T, 4>(a, fw, fa, st, do_fwd, vss);
+    case 6: return launch_pipeline_N<T, 6>(a, fw, fa, st, do_fwd, vss);
+    case 8: return launch_pipeline_N<T, 8>(a, fw, fa, st, do_fwd, vss);
+    case 12: return launch_pipeline_N<T, 12>(a, fw, fa, st, do_fwd, vss);
+    case 16: return launch_pipeline_N<T, 16>(a, fw, fa, st, do_fwd, vss);
+    case 18: return launch_pipeline_N<T, 18>(a, fw, fa, st, do_fwd, vss);
+    case 24: return launch_pipeline_N<T, 24>(a, fw, fa, st, do_fwd, vss);
+    case 32: return launch_pipeline_N<T, 32>(a, fw, fa, st, do_fwd, vss);
+    case 36: return launch_pipeline_N<T, 36>(a, fw, fa, st, do_fwd, vss);
+    case 48: return launch_pipeline_N<T, 48>(a, fw, fa, st, do_fwd, vss);
     default: return hipErrorInvalidValue;
   }
 }
 
 hipError_t launch_pipeline(const dgfs_plan_s *pl, const PipeArgs &a, const FwdArgs &fw, const FinalArgs &fa,
                            hipStream_t st, bool do_fwd) {
-  if (pl->precision == DGFS_FP64) return launch_pipeline_T<double>(pl->N, a, fw, fa, st, do_fwd);
-  return launch_pipeline_T<float>(pl->N, a, fw, fa, st, do_fwd);
+  if (pl->precision == DGFS_FP64) return launch_pipeline_T<double>(pl->N, a, fw, fa, st, do_fwd, !pl->vhs);
+  return launch_pipeline_T<float>(pl->N, a, fw, fa, st, do_fwd, !pl->vhs);
 }
 
 static size_t align256(size_t b) { return (b + 255) / 256 * 256; }
@@ -68,14 +80,19 @@ int max_evals_per_chunk() {
 
 int chunk_nodes(const dgfs_plan_s *pl, int64_t n_nodes, int n_pairs) {
   int64_t b = std::max<int64_t>(1, max_evals_per_chunk() / n_pairs);
+  // keep a chunk's intermediates within 8 GiB (the VSS path stores every (r, m) term)
+  const size_t per_node = pipeline_bytes(pl, 1, n_pairs, std::min(pl->ns, 2 * n_pairs));
+  const int64_t cap = std::max<int64_t>(1, (int64_t)((size_t)8 << 30) / (int64_t)per_node);
+  b = std::min(b, cap);
   return (int)std::max<int64_t>(1, std::min<int64_t>(b, n_nodes));
 }
 
 size_t pipeline_bytes(const dgfs_plan_s *pl, int B, int n_pairs, int nz) {
   const size_t n3 = (size_t)pl->N * pl->N * pl->N, c = 2 * pl->elt();
   const size_t E = (size_t)B * n_pairs;
+  const size_t nc = pl->vhs ? (size_t)pl->Nr : (size_t)pl->Nr * pl->M;  // C arrays per evaluation
   return align256((size_t)B * nz * n3 * c) + align256(E * 2 * pl->Nr * pl->Sx * n3 * c) +
-         align256(E * pl->Nr * n3 * c) + align256(E * 2 * n3 * c);
+         align256(E * nc * n3 * c) + align256(E * 2 * n3 * c);
 }
 
 void pipeline_carve(const dgfs_plan_s *pl, int B, int n_pairs, int nz, void *ws, PipeArgs &a) {
@@ -87,7 +104,7 @@ void pipeline_carve(const dgfs_plan_s *pl, int B, int n_pairs, int nz, void *ws,
   a.X = p;
   p += align256(E * 2 * pl->Nr * pl->Sx * n3 * c);
   a.Cb = p;
-  p += align256(E * pl->Nr * n3 * c);
+  p += align256(E * (pl->vhs ? (size_t)pl->Nr : (size_t)pl->Nr * pl->M) * n3 * c);
   a.V = p;
 }
 
@@ -99,6 +116,7 @@ void pipeline_common(const dgfs_plan_s *pl, PipeArgs &a) {
   a.pairs = pl->pair_dev;
   a.wm = pl->wm_dev;
   a.sidx = pl->sidx_dev;
+  a.sx_zero = pl->sxz_dev;
 }
 
 }  // namespace dgfs

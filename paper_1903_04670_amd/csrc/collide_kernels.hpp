@@ -39,6 +39,7 @@ struct PipeArgs {
   const PairDev *pairs;
   const void *wm;
   const int *sidx;
+  const int *sx_zero;  // [Sx]: 1 if that sigma_x value is zero (X then independent of r)
   void *Z, *X, *Cb, *V;
 };
 
@@ -60,6 +61,18 @@ struct FinalArgs {
 
 __device__ __forceinline__ int wave_idx(int j, int N) { return j < N / 2 ? j : j - N; }
 
+// Load from a table that every lane reads at the same address: through the
+// constant address space, so the compiler issues scalar (SMEM) loads.
+template <typename V>
+__device__ __forceinline__ V uload(const V *p, size_t i) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  using CP = const __attribute__((address_space(4))) V *;
+  return reinterpret_cast<CP>(reinterpret_cast<uintptr_t>(p))[i];
+#else
+  return p[i];
+#endif
+}
+
 // Neumaier-compensated accumulation (used by the FP32 path).
 template <typename T> struct Acc {
   T s, c;
@@ -73,12 +86,11 @@ template <typename T> __device__ __forceinline__ void acc_add(T &s, T &c, T x) {
 // ------------------------------------------------------------------ k_fwd_yz
 // One (node, slot, x-plane) per group of N threads; G planes per block.
 template <typename T, int N, int G>
-__global__ void __launch_bounds__(G * N) k_fwd_yz(FwdArgs a) {
-  __shared__ C<T> lds[G][N][N + 1];
-  const int g = threadIdx.x / N, t = threadIdx.x % N;
-  const int plane = blockIdx.x * G + g;   // over N x-planes * n_nodes * nz
+__device__ __forceinline__ void fwd_yz_body(const FwdArgs &a, int bx, int tid, C<T> (*lds)[N][N + 1]) {
+  const int g = tid / N, t = tid % N;
+  const int plane = bx * G + g;   // over N x-planes * n_nodes * nz
   const int jobs = N * a.n_nodes * a.nz;
-  const bool active = plane < jobs;
+  const bool active = g < G && plane < jobs;
   const int jx = plane % N, job = plane / N;
   const int node = job / a.nz, slot = job % a.nz;
   const size_t n3 = (size_t)N * N * N;
@@ -107,95 +119,123 @@ __global__ void __launch_bounds__(G * N) k_fwd_yz(FwdArgs a) {
     for (int y = 0; y < N; ++y) Z[y * N + t] = col[y];
   }
 }
+template <typename T, int N, int G>
+__global__ void __launch_bounds__(G * N) k_fwd_yz(FwdArgs a) {
+  __shared__ C<T> lds[G][N][N + 1];
+  fwd_yz_body<T, N, G>(a, blockIdx.x, threadIdx.x, lds);
+}
 
 // ------------------------------------------------------------------ k_shift_x
-// Thread = x-line (y, z) of one (eval, side); loops over r and the distinct
-// sigma_x values.
+// Lane pair (pencil, p) = x-line (y, z) of one (eval, side): forward x
+// transform of Z (decimation in time: lane p loads x = 2n + p and ends with
+// frequencies p*N/2 + k), then for every r and distinct sigma_x the phase
+// and the inverse transform (decimation in frequency back to x = 2n + p).
 template <typename T, int N>
-__global__ void __launch_bounds__(64) k_shift_x(PipeArgs a) {
-  const int pencil = blockIdx.x * 64 + threadIdx.x;
-  const int side = blockIdx.y;
-  const int e = blockIdx.z;
-  if (pencil >= N * N) return;
+__device__ __forceinline__ void shift_x_body(const PipeArgs &a, int bx, int side, int e, int tid) {
+  constexpr int H = N / 2;
+  const int pencil = bx * 32 + (tid >> 1), p = tid & 1;
+  const bool valid = pencil < N * N;
+  const int pc = valid ? pencil : 0;  // idle lanes still take part in the lane swaps
   const int node = e / a.n_pairs, slot = e % a.n_pairs;
   const PairDev pd = a.pairs[a.pair_id[slot]];
   const size_t n3 = (size_t)N * N * N;
   const int zs = side == 0 ? a.zp[slot] : a.zq[slot];
   const C<T> *Z = static_cast<const C<T> *>(a.Z) + ((size_t)node * a.nz + zs) * n3;
-  C<T> F[N];
+  C<T> F[H];
 #pragma unroll
-  for (int x = 0; x < N; ++x) F[x] = Z[(size_t)x * N * N + pencil];
-  fft<N, -1>(F);
+  for (int n = 0; n < H; ++n) F[n] = Z[(size_t)(2 * n + p) * N * N + pc];
+  fft_pair<N, -1>(F, p);
   const C<T> *px = static_cast<const C<T> *>(pd.px) + (size_t)side * a.Nr * a.Sx * N;
   C<T> *X = static_cast<C<T> *>(a.X) + ((size_t)e * 2 + side) * a.Nr * a.Sx * n3;
   for (int rs = 0; rs < a.Nr * a.Sx; ++rs) {
-    const C<T> *ph = px + (size_t)rs * N;
-    C<T> w[N];
+    if (rs >= a.Sx && a.sx_zero[rs % a.Sx]) continue;
+    const C<T> *ph = px + (size_t)rs * N + p * H;
+    C<T> w[H];
 #pragma unroll
-    for (int x = 0; x < N; ++x) w[x] = cmul(F[x], ph[x]);
-    fft<N, +1>(w);
+    for (int k = 0; k < H; ++k) w[k] = cmul(F[k], ph[k]);
+    fft_pair_dif<N, +1>(w, p);
     C<T> *dst = X + (size_t)rs * n3;
+    if (valid) {
 #pragma unroll
-    for (int x = 0; x < N; ++x) dst[(size_t)x * N * N + pencil] = w[x];
+      for (int k = 0; k < H; ++k) dst[(size_t)(2 * k + p) * N * N + pc] = w[k];
+    }
   }
+}
+template <typename T, int N>
+__global__ void __launch_bounds__(64) k_shift_x(PipeArgs a) {
+  shift_x_body<T, N>(a, blockIdx.x, blockIdx.y, blockIdx.z, threadIdx.x);
 }
 
 // ------------------------------------------------------------------ k_gain_yz
-// Block = G groups of N threads on one (eval, r, x-plane); group g takes the
-// directions m = g, g+G, ...  Thread t owns column z = t in the y pass and row
-// y = t in the z pass, product and accumulation.
+// Block = G groups of 2N threads on one (eval, r, x-plane); group g takes the
+// directions m = g, g+G, ...  Every length-N pencil is split over a lane pair
+// (fft_pair).  Per direction and side: the column (y) pass reads X coalesced
+// (lane pair (c, p) holds rows y = 2n+p of column z = c), transforms, and
+// writes the column to the group's LDS buffer; the row (z) pass reads row
+// y = c back (z = 2n+p) and transforms it.  u1's row half stays in
+// registers while u2 reuses the buffer; the product is accumulated into the
+// row-half accumulator P (compensated in FP32).
 template <typename T, int N, int G>
-__global__ void __launch_bounds__(G * N) k_gain_yz(PipeArgs a) {
-  __shared__ C<T> lds[G][N][N + 1];
-  const int g = threadIdx.x / N, t = threadIdx.x % N;
-  const int jx = blockIdx.x, r = blockIdx.y, e = blockIdx.z;
+__device__ __forceinline__ void gain_yz_body(const PipeArgs &a, int jx, int r, int e, int tid, C<T> (*lds)[N][N + 1]) {
+  constexpr int H = N / 2;
+  const int g = tid / (2 * N), l = tid % (2 * N);
+  const int c = l >> 1, p = l & 1;  // column (then row) index, lane parity
+  const bool in_group = g < G;       // threads beyond G groups only join the barriers
   const int slot = e % a.n_pairs;
   const PairDev pd = a.pairs[a.pair_id[slot]];
   const size_t n3 = (size_t)N * N * N;
   const C<T> *X = static_cast<const C<T> *>(a.X) + (size_t)e * 2 * a.Nr * a.Sx * n3;
   const T *wm = static_cast<const T *>(a.wm);
   const C<T> *pyz = static_cast<const C<T> *>(pd.pyz);
-  C<T> P[N], Pc[N], u1[N];
+  C<T> P[H], u1[H];
+  T Pcx[sizeof(T) == 4 ? H : 1], Pcy[sizeof(T) == 4 ? H : 1];
 #pragma unroll
-  for (int z = 0; z < N; ++z) P[z] = Pc[z] = C<T>{0, 0};
+  for (int k = 0; k < H; ++k) P[k] = C<T>{0, 0};
+  if constexpr (sizeof(T) == 4) {
+#pragma unroll
+    for (int k = 0; k < H; ++k) Pcx[k] = Pcy[k] = 0;
+  }
   const int iters = (a.M + G - 1) / G;
   for (int it = 0; it < iters; ++it) {
     const int m = it * G + g;
-    const bool active = m < a.M;
-#pragma unroll
+    const bool active = in_group && m < a.M;
+    const int s = active ? a.sidx[m] : 0;
+    const int rx = a.sx_zero[s] ? 0 : r;  // X of a zero x-component does not depend on r
+#pragma unroll 1
     for (int side = 0; side < 2; ++side) {
       if (active) {
-        const int s = a.sidx[m];
-        const C<T> *src = X + (((size_t)side * a.Nr + r) * a.Sx + s) * n3 + (size_t)jx * N * N;
+        const C<T> *src = X + (((size_t)side * a.Nr + rx) * a.Sx + s) * n3 + (size_t)jx * N * N;
         const C<T> *ph = pyz + (((size_t)side * a.Nr + r) * a.M + m) * 2 * N;
-        const C<T> zph = ph[N + t];
-        C<T> col[N];
+        const C<T> zph = ph[N + c];
+        C<T> h[H];
 #pragma unroll
-        for (int y = 0; y < N; ++y) col[y] = cmul(src[y * N + t], cmul(ph[y], zph));
-        fft<N, +1>(col);
+        for (int n = 0; n < H; ++n) h[n] = src[(2 * n + p) * N + c];
 #pragma unroll
-        for (int y = 0; y < N; ++y) lds[g][y][t] = col[y];
+        for (int n = 0; n < H; ++n) h[n] = cmul(h[n], cmul(ph[2 * n + p], zph));
+        fft_pair<N, +1>(h, p);
+#pragma unroll
+        for (int k = 0; k < H; ++k) lds[g][p * H + k][c] = h[k];
       }
       __syncthreads();
       if (active) {
-        C<T> row[N];
+        C<T> h[H];
 #pragma unroll
-        for (int z = 0; z < N; ++z) row[z] = lds[g][t][z];
-        fft<N, +1>(row);
+        for (int n = 0; n < H; ++n) h[n] = lds[g][c][2 * n + p];
+        fft_pair<N, +1>(h, p);
         if (side == 0) {
 #pragma unroll
-          for (int z = 0; z < N; ++z) u1[z] = row[z];
+          for (int k = 0; k < H; ++k) u1[k] = h[k];
         } else {
-          const T w = wm[m];
+          const T w = uload(wm, m);
 #pragma unroll
-          for (int z = 0; z < N; ++z) {
-            C<T> pr = cmul(u1[z], row[z]);
+          for (int k = 0; k < H; ++k) {
+            const C<T> pr = cmul(u1[k], h[k]);
             if constexpr (sizeof(T) == 4) {
-              acc_add(P[z].x, Pc[z].x, w * pr.x);
-              acc_add(P[z].y, Pc[z].y, w * pr.y);
+              acc_add(P[k].x, Pcx[k], w * pr.x);
+              acc_add(P[k].y, Pcy[k], w * pr.y);
             } else {
-              P[z].x += w * pr.x;
-              P[z].y += w * pr.y;
+              P[k].x += w * pr.x;
+              P[k].y += w * pr.y;
             }
           }
         }
@@ -203,111 +243,135 @@ __global__ void __launch_bounds__(G * N) k_gain_yz(PipeArgs a) {
       __syncthreads();
     }
   }
-  // combine the groups' partial sums in group order, then FFT_yz
-  if constexpr (G > 1) {
-    if (g > 0) {
+  if constexpr (sizeof(T) == 4) {
 #pragma unroll
-      for (int z = 0; z < N; ++z) lds[g][t][z] = C<T>{P[z].x + Pc[z].x, P[z].y + Pc[z].y};
-    }
-    __syncthreads();
-    if (g == 0) {
-#pragma unroll
-      for (int z = 0; z < N; ++z) {
-        T sx = P[z].x, cx = Pc[z].x, sy = P[z].y, cy = Pc[z].y;
-        for (int h = 1; h < G; ++h) {
-          C<T> v = lds[h][t][z];
-          if constexpr (sizeof(T) == 4) {
-            acc_add(sx, cx, v.x);
-            acc_add(sy, cy, v.y);
-          } else {
-            sx += v.x;
-            sy += v.y;
-          }
-        }
-        P[z] = C<T>{sx, sy};
-        Pc[z] = C<T>{cx, cy};
-      }
-    }
-    __syncthreads();
+    for (int k = 0; k < H; ++k) P[k] = C<T>{P[k].x + Pcx[k], P[k].y + Pcy[k]};
   }
-  if (g == 0) {
+  // P (row y = c, z = p*H + k) to LDS; groups combined in group order
+  if (in_group) {
 #pragma unroll
-    for (int z = 0; z < N; ++z) P[z] = C<T>{P[z].x + Pc[z].x, P[z].y + Pc[z].y};
-    fft<N, -1>(P);
-#pragma unroll
-    for (int z = 0; z < N; ++z) lds[0][t][z] = P[z];
+    for (int k = 0; k < H; ++k) lds[g][c][p * H + k] = P[k];
   }
   __syncthreads();
   if (g == 0) {
-    C<T> col[N];
+    // row pass of the forward transform: read z = 2n + p, summing the groups
+    C<T> h[H];
 #pragma unroll
-    for (int y = 0; y < N; ++y) col[y] = lds[0][y][t];
-    fft<N, -1>(col);
+    for (int n = 0; n < H; ++n) {
+      T sx = lds[0][c][2 * n + p].x, sy = lds[0][c][2 * n + p].y, cx = 0, cy = 0;
+      for (int q = 1; q < G; ++q) {
+        const C<T> v = lds[q][c][2 * n + p];
+        if constexpr (sizeof(T) == 4) {
+          acc_add(sx, cx, v.x);
+          acc_add(sy, cy, v.y);
+        } else {
+          sx += v.x;
+          sy += v.y;
+        }
+      }
+      h[n] = C<T>{sx + cx, sy + cy};
+    }
+    fft_pair<N, -1>(h, p);
+#pragma unroll
+    for (int k = 0; k < H; ++k) P[k] = h[k];
+  }
+  __syncthreads();
+  if (g == 0) {
+#pragma unroll
+    for (int k = 0; k < H; ++k) lds[0][c][p * H + k] = P[k];
+  }
+  __syncthreads();
+  if (g == 0) {
+    C<T> h[H];
+#pragma unroll
+    for (int n = 0; n < H; ++n) h[n] = lds[0][2 * n + p][c];
+    fft_pair<N, -1>(h, p);
     C<T> *dst = static_cast<C<T> *>(a.Cb) + ((size_t)e * a.Nr + r) * n3 + (size_t)jx * N * N;
 #pragma unroll
-    for (int y = 0; y < N; ++y) dst[y * N + t] = col[y];
+    for (int k = 0; k < H; ++k) dst[(p * H + k) * N + c] = h[k];
   }
+}
+template <typename T, int N, int G>
+__global__ void __launch_bounds__(G * 2 * N) k_gain_yz(PipeArgs a) {
+  __shared__ C<T> lds[G][N][N + 1];
+  gain_yz_body<T, N, G>(a, blockIdx.x, blockIdx.y, blockIdx.z, threadIdx.x, lds);
 }
 
 // ------------------------------------------------------------------ k_gain_x
-// Thread = x-line (y, z) of one eval: QG = sum_r g_r(|k|) FFT_x C_r, then
+// Lane pair = x-line (y, z) of one eval: QG = sum_r g_r(|k|) FFT_x C_r, then
 // V1 = iFFT_x QG and V2 = iFFT_x(c(|k|) FFT_x Z_q).
 template <typename T, int N>
-__global__ void __launch_bounds__(64) k_gain_x(PipeArgs a) {
-  const int pencil = blockIdx.x * 64 + threadIdx.x;
-  const int e = blockIdx.y;
-  if (pencil >= N * N) return;
+__device__ __forceinline__ void gain_x_body(const PipeArgs &a, int bx, int e, int tid) {
+  constexpr int H = N / 2;
+  const int pencil = bx * 32 + (tid >> 1), p = tid & 1;
+  const bool valid = pencil < N * N;
+  const int pc = valid ? pencil : 0;
   const int node = e / a.n_pairs, slot = e % a.n_pairs;
   const PairDev pd = a.pairs[a.pair_id[slot]];
   const size_t n3 = (size_t)N * N * N;
   const int K2 = 3 * (N / 2) * (N / 2) + 1;
-  const int vy = wave_idx(pencil / N, N), vz = wave_idx(pencil % N, N);
+  const int vy = wave_idx(pc / N, N), vz = wave_idx(pc % N, N);
   const int kyz = vy * vy + vz * vz;
   const T *gt = static_cast<const T *>(pd.gtab);
   const C<T> *Cb = static_cast<const C<T> *>(a.Cb) + (size_t)e * a.Nr * n3;
-  C<T> Q[N], Qc[N];
+  C<T> Q[H];
+  T Qcx[sizeof(T) == 4 ? H : 1], Qcy[sizeof(T) == 4 ? H : 1];
 #pragma unroll
-  for (int x = 0; x < N; ++x) Q[x] = Qc[x] = C<T>{0, 0};
+  for (int k = 0; k < H; ++k) Q[k] = C<T>{0, 0};
+  if constexpr (sizeof(T) == 4) {
+#pragma unroll
+    for (int k = 0; k < H; ++k) Qcx[k] = Qcy[k] = 0;
+  }
   for (int r = 0; r < a.Nr; ++r) {
-    C<T> w[N];
+    C<T> w[H];
     const C<T> *src = Cb + (size_t)r * n3;
 #pragma unroll
-    for (int x = 0; x < N; ++x) w[x] = src[(size_t)x * N * N + pencil];
-    fft<N, -1>(w);
+    for (int n = 0; n < H; ++n) w[n] = src[(size_t)(2 * n + p) * N * N + pc];
+    fft_pair<N, -1>(w, p);
     const T *g = gt + (size_t)r * K2 + kyz;
 #pragma unroll
-    for (int x = 0; x < N; ++x) {
-      const int vx = wave_idx(x, N);
+    for (int k = 0; k < H; ++k) {
+      const int vx = wave_idx(p * H + k, N);
       const T gv = g[vx * vx];
       if constexpr (sizeof(T) == 4) {
-        acc_add(Q[x].x, Qc[x].x, gv * w[x].x);
-        acc_add(Q[x].y, Qc[x].y, gv * w[x].y);
+        acc_add(Q[k].x, Qcx[k], gv * w[k].x);
+        acc_add(Q[k].y, Qcy[k], gv * w[k].y);
       } else {
-        Q[x].x += gv * w[x].x;
-        Q[x].y += gv * w[x].y;
+        Q[k].x += gv * w[k].x;
+        Q[k].y += gv * w[k].y;
       }
     }
   }
+  if constexpr (sizeof(T) == 4) {
 #pragma unroll
-  for (int x = 0; x < N; ++x) Q[x] = C<T>{Q[x].x + Qc[x].x, Q[x].y + Qc[x].y};
-  fft<N, +1>(Q);
+    for (int k = 0; k < H; ++k) Q[k] = C<T>{Q[k].x + Qcx[k], Q[k].y + Qcy[k]};
+  }
+  fft_pair_dif<N, +1>(Q, p);
   C<T> *V = static_cast<C<T> *>(a.V) + (size_t)e * 2 * n3;
+  if (valid) {
 #pragma unroll
-  for (int x = 0; x < N; ++x) V[(size_t)x * N * N + pencil] = Q[x];
+    for (int k = 0; k < H; ++k) V[(size_t)(2 * k + p) * N * N + pc] = Q[k];
+  }
   // loss: c(|k|) * FFT_x Z_q, back along x
   const C<T> *Zq = static_cast<const C<T> *>(a.Z) + ((size_t)node * a.nz + a.zq[slot]) * n3;
 #pragma unroll
-  for (int x = 0; x < N; ++x) Q[x] = Zq[(size_t)x * N * N + pencil];
-  fft<N, -1>(Q);
+  for (int n = 0; n < H; ++n) Q[n] = Zq[(size_t)(2 * n + p) * N * N + pc];
+  fft_pair<N, -1>(Q, p);
   const T *ct = static_cast<const T *>(pd.ctab) + kyz;
 #pragma unroll
-  for (int x = 0; x < N; ++x) {
-    const int vx = wave_idx(x, N);
-    Q[x] = cscale(Q[x], ct[vx * vx]);
+  for (int k = 0; k < H; ++k) {
+    const int vx = wave_idx(p * H + k, N);
+    Q[k] = cscale(Q[k], ct[vx * vx]);
   }
-  fft<N, +1>(Q);
+  fft_pair_dif<N, +1>(Q, p);
+  if (valid) {
 #pragma unroll
-  for (int x = 0; x < N; ++x) V[n3 + (size_t)x * N * N + pencil] = Q[x];
+    for (int k = 0; k < H; ++k) V[n3 + (size_t)(2 * k + p) * N * N + pc] = Q[k];
+  }
+}
+template <typename T, int N>
+__global__ void __launch_bounds__(64) k_gain_x(PipeArgs a) {
+  gain_x_body<T, N>(a, blockIdx.x, blockIdx.y, threadIdx.x);
 }
 
 // ------------------------------------------------------------------ k_final_yz
@@ -315,12 +379,12 @@ __global__ void __launch_bounds__(64) k_gain_x(PipeArgs a) {
 // of beta Re(iFFT_yz V1 - f^p iFFT_yz V2).  Rows first (staged through LDS),
 // then columns so the output and f^p are accessed coalesced.
 template <typename T, int N, int G>
-__global__ void __launch_bounds__(G * N) k_final_yz(PipeArgs a, FinalArgs fa) {
-  __shared__ C<T> lds[G][N][N + 1];
-  const int g = threadIdx.x / N, t = threadIdx.x % N;
-  const int plane = blockIdx.x * G + g;
+__device__ __forceinline__ void final_yz_body(const PipeArgs &a, const FinalArgs &fa, int bx, int tid,
+                                              C<T> (*lds)[N][N + 1]) {
+  const int g = tid / N, t = tid % N;
+  const int plane = bx * G + g;
   const int jobs = N * a.n_nodes * fa.n_out;
-  const bool active = plane < jobs;
+  const bool active = g < G && plane < jobs;
   const int jx = plane % N, job = plane / N;
   const int node = job / fa.n_out, o = job % fa.n_out;
   const size_t n3 = (size_t)N * N * N;
@@ -373,6 +437,11 @@ __global__ void __launch_bounds__(G * N) k_final_yz(PipeArgs a, FinalArgs fa) {
       else out[y * N + t] = acc[y];
     }
   }
+}
+template <typename T, int N, int G>
+__global__ void __launch_bounds__(G * N) k_final_yz(PipeArgs a, FinalArgs fa) {
+  __shared__ C<T> lds[G][N][N + 1];
+  final_yz_body<T, N, G>(a, fa, blockIdx.x, threadIdx.x, lds);
 }
 
 }  // namespace dgfs

@@ -211,4 +211,61 @@ DGFS_HD void fft(cplx<T> (&x)[N]) {
   FFTView<N, DIR, 0, 1, N, T>::run(x);
 }
 
+
+// ---------------------------------------------------------------- paired lanes
+// A length-N transform split over two adjacent lanes (lane parity p): on
+// entry each lane holds its decimated half x[2n + p], n < N/2; on exit lane p
+// holds X[p N/2 + k], k < N/2.  The two halves are combined by one radix-2
+// stage whose partner values come through a DPP quad permutation [1,0,3,2]
+// (lane t <-> lane t^1), so no LDS is used.
+namespace detail {
+__device__ __forceinline__ float swap_pair(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xB1, 0xF, 0xF, false));
+}
+__device__ __forceinline__ double swap_pair(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffffLL), 0xB1, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), 0xB1, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+template <int N, int DIR, int K, int H, typename T>
+struct TwHalf {
+  static DGFS_HD void run(cplx<T> (&h)[H]) {
+    if constexpr (K < H) {
+      h[K] = twiddle<N, DIR, K>(h[K]);
+      TwHalf<N, DIR, K + 1, H, T>::run(h);
+    }
+  }
+};
+}  // namespace detail
+
+template <int N, int DIR, typename T>
+__device__ __forceinline__ void fft_pair(cplx<T> (&h)[N / 2], int p) {
+  static_assert(N % 2 == 0, "paired transform needs even N");
+  fft<N / 2, DIR>(h);
+  if (p) detail::TwHalf<N, DIR, 0, N / 2, T>::run(h);
+  const T sg = p ? (T)-1 : (T)1;
+#pragma unroll
+  for (int k = 0; k < N / 2; ++k) {
+    const cplx<T> o{detail::swap_pair(h[k].x), detail::swap_pair(h[k].y)};
+    h[k] = cplx<T>{sg * h[k].x + o.x, sg * h[k].y + o.y};
+  }
+}
+
+// Decimation-in-frequency counterpart: on entry lane p holds x[p N/2 + n]
+// (natural halves), on exit lane p holds X[2k + p] (decimated).
+template <int N, int DIR, typename T>
+__device__ __forceinline__ void fft_pair_dif(cplx<T> (&h)[N / 2], int p) {
+  static_assert(N % 2 == 0, "paired transform needs even N");
+  const T sg = p ? (T)-1 : (T)1;
+#pragma unroll
+  for (int n = 0; n < N / 2; ++n) {
+    const cplx<T> o{detail::swap_pair(h[n].x), detail::swap_pair(h[n].y)};
+    // lane 0: x[n] + x[n+N/2]; lane 1: x[n] - x[n+N/2] (then twiddled)
+    h[n] = cplx<T>{o.x + sg * h[n].x, o.y + sg * h[n].y};
+  }
+  if (p) detail::TwHalf<N, DIR, 0, N / 2, T>::run(h);
+  fft<N / 2, DIR>(h);
+}
+
 }  // namespace dgfs

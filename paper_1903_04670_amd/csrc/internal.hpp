@@ -19,6 +19,7 @@ struct PairDev {
   const void *pyz;   // [2][Nr][M][2][N] cplx: side 0 e^{+i th_q sigma_a v}, side 1 e^{-i th_p sigma_a v}; a = y, z
   const void *gtab;  // VHS: [Nr][K2] real  w_r b_r(|k|)/N^3, indexed by |k|^2
   const void *ctab;  // [K2] real  c(|k|)/N^3
+  const void *btab;  // VSS: [Nr][M][N^3] cplx  w_r w_m b_rm(k)/N^3 (natural wave order); else NULL
   double beta;
 };
 
@@ -39,7 +40,8 @@ struct dgfs_plan_s {
   std::vector<double> sx_val;  // [Sx]
   std::vector<int> sx_idx;     // [M]
   std::vector<dgfs::PairHost> pairs;  // [ns*ns], p-major
-  bool vhs = true;
+  bool vhs = true;      // every pair has alpha == 1 (sigma-independent gain table)
+  void *vss_dev = nullptr;  // VSS gain tables of all pairs (separate allocation)
   // device memory owned by the plan
   void *dev = nullptr;
   size_t dev_bytes = 0;
@@ -47,6 +49,7 @@ struct dgfs_plan_s {
   std::vector<dgfs::PairDev> pair_host;  // same pointers, host copy
   const void *wm_dev = nullptr;        // [M] T sphere weights
   const int *sidx_dev = nullptr;       // [M]
+  const int *sxz_dev = nullptr;        // [Sx] zero-x-component flags
   // nodal DG operators on P+1 Gauss-Lobatto points (row-major (P+1)^2)
   std::vector<double> dg_r, dg_Dr, dg_Minv;
   // (C C^T)^{-1} of the conservation constraints of all species (ns+4)^2

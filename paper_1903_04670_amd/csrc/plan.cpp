@@ -69,6 +69,7 @@ static double sinc(double x) { return x == 0.0 ? 1.0 : std::sin(x) / x; }
 static int wave(int j, int N) { return j < N / 2 ? j : j - N; }
 
 bool dg_setup(int P, std::vector<double> &r, std::vector<double> &Dr, std::vector<double> &Minv);
+dgfs_status build_vss_tables(dgfs_plan_s *pl);
 bool projection_ginv(const dgfs_plan_s *pl, const std::vector<int> &species, std::vector<double> &G);
 
 }  // namespace dgfs
@@ -202,11 +203,6 @@ extern "C" dgfs_status dgfs_plan_create(const dgfs_params *prm, dgfs_plan *out) 
         ph.wrho[r] = 0.5 * ph.R * glw[r];
       }
     }
-  if (!pl->vhs) {
-    set_error("VSS kernels (alpha != 1) are not supported by this build");
-    delete pl;
-    return DGFS_EUNSUPPORTED;
-  }
 
   // ---- tables, built in FP64 on the host
   const int K2 = pl->K2(), Sx = pl->Sx, npair = ns * ns;
@@ -284,7 +280,7 @@ extern "C" dgfs_status dgfs_plan_create(const dgfs_params *prm, dgfs_plan *out) 
   const size_t nvals = hostbuf.size();
   const size_t bytes_vals = ((nvals * e + 255) / 256) * 256;
   const size_t bytes_pairs = ((npair * sizeof(PairDev) + 255) / 256) * 256;
-  const size_t bytes_sidx = ((M * sizeof(int) + 255) / 256) * 256;
+  const size_t bytes_sidx = (((M + pl->Sx) * sizeof(int) + 255) / 256) * 256;
   pl->dev_bytes = bytes_vals + bytes_pairs + bytes_sidx;
   hipError_t he = hipMalloc(&pl->dev, pl->dev_bytes);
   if (he != hipSuccess) {
@@ -310,13 +306,30 @@ extern "C" dgfs_status dgfs_plan_create(const dgfs_params *prm, dgfs_plan *out) 
   }
   std::memcpy(img.data() + bytes_vals, pl->pair_host.data(), npair * sizeof(PairDev));
   std::memcpy(img.data() + bytes_vals + bytes_pairs, pl->sx_idx.data(), M * sizeof(int));
+  {
+    std::vector<int> z(pl->Sx);
+    for (int s = 0; s < pl->Sx; ++s) z[s] = pl->sx_val[s] == 0.0 ? 1 : 0;
+    std::memcpy(img.data() + bytes_vals + bytes_pairs + M * sizeof(int), z.data(), pl->Sx * sizeof(int));
+  }
   pl->pair_dev = reinterpret_cast<PairDev *>(base + bytes_vals);
   pl->wm_dev = base + off_wm * e;
   pl->sidx_dev = reinterpret_cast<const int *>(base + bytes_vals + bytes_pairs);
+  pl->sxz_dev = pl->sidx_dev + M;
+  if (!pl->vhs) {
+    dgfs_status vs = build_vss_tables(pl);
+    if (vs != DGFS_OK) {
+      (void)hipFree(pl->dev);
+      delete pl;
+      return vs;
+    }
+    for (int pr = 0; pr < npair; ++pr)
+      std::memcpy(img.data() + bytes_vals + pr * sizeof(PairDev), &pl->pair_host[pr], sizeof(PairDev));
+  }
   he = hipMemcpy(pl->dev, img.data(), pl->dev_bytes, hipMemcpyHostToDevice);
   if (he != hipSuccess) {
     set_error("plan tables: upload failed: %s", hipGetErrorString(he));
     hipFree(pl->dev);
+    if (pl->vss_dev) hipFree(pl->vss_dev);
     delete pl;
     return DGFS_EHIP;
   }
@@ -330,6 +343,7 @@ extern "C" void dgfs_plan_destroy(dgfs_plan plan) {
   if (!plan) return;
   dgfs::destroy_graph_cache(plan);
   if (plan->dev) (void)hipFree(plan->dev);
+  if (plan->vss_dev) (void)hipFree(plan->vss_dev);
   delete plan;
 }
 
@@ -359,6 +373,23 @@ extern "C" dgfs_status dgfs_plan_table(dgfs_plan pl, int32_t p, int32_t q, int32
     case 3:
     case 4: {
       if (!need((int64_t)Nr * M * n3)) return DGFS_EINVAL;
+      if (!pl->vhs) {  // copy the device table back, undoing w_r w_m / N^3
+        const size_t cnt = (size_t)Nr * M * n3 * 2;
+        std::vector<unsigned char> buf(cnt * pl->elt());
+        hipError_t he = hipMemcpy(buf.data(), pl->pair_host[p * pl->ns + q].btab, buf.size(), hipMemcpyDeviceToHost);
+        if (he != hipSuccess) return hip_status(he, "dgfs_plan_table");
+        for (int r = 0; r < Nr; ++r)
+          for (int m = 0; m < M; ++m) {
+            const double sc = (double)n3 / (ph.wrho[r] * pl->wsig[m]);
+            for (int64_t k = 0; k < n3; ++k) {
+              const size_t i = 2 * (((size_t)r * M + m) * n3 + k) + (which == 4 ? 1 : 0);
+              const double v = pl->precision == DGFS_FP64 ? reinterpret_cast<double *>(buf.data())[i]
+                                                          : (double)reinterpret_cast<float *>(buf.data())[i];
+              out[((int64_t)r * M + m) * n3 + k] = v * sc;
+            }
+          }
+        return DGFS_OK;
+      }
       for (int r = 0; r < Nr; ++r)
         for (int m = 0; m < M; ++m)
           for (int i = 0; i < N; ++i)

@@ -44,7 +44,7 @@ static hipError_t launch_vjp_N(const VjpArgs &v, const FwdArgs &fw, hipStream_t 
   DGFS_LAUNCH("k_fwd_yz", (k_fwd_yz<T, N, G>), dim3((planes_f + G - 1) / G), dim3(G * N), 0, st, fw);
   const int planes_w = N * a.n_nodes * 2;
   DGFS_LAUNCH("k_inv_yz", (k_inv_yz<T, N, G>), dim3((planes_w + G - 1) / G), dim3(G * N), 0, st, v);
-  DGFS_LAUNCH("k_shift_x", (k_shift_x<T, N>), dim3(pb, 2, E), dim3(64), 0, st, a);
+  DGFS_LAUNCH("k_shift_x", (k_shift_x<T, N>), dim3((N * N + 31) / 32, 2, E), dim3(64), 0, st, a);
   DGFS_LAUNCH("k_vjp_v", (k_vjp_v<T, N>), dim3(pb, E), dim3(64), 0, st, v);
   DGFS_LAUNCH("k_vjp_yz", (k_vjp_yz<T, N>), dim3(N, a.Nr, E), dim3(N), 0, st, v);
   DGFS_LAUNCH("k_vjp_x", (k_vjp_x<T, N>), dim3(pb, E), dim3(64), 0, st, v);
@@ -82,6 +82,7 @@ extern "C" dgfs_status dgfs_collide_vjp(dgfs_plan pl, int64_t n_nodes, int32_t p
   if (n_nodes < 0) { set_error("dgfs_collide_vjp: n_nodes < 0"); return DGFS_EINVAL; }
   if (p < 0 || q < 0 || p >= pl->ns || q >= pl->ns) { set_error("dgfs_collide_vjp: species out of range"); return DGFS_EINVAL; }
   if (flags & ~DGFS_ACCUMULATE) { set_error("dgfs_collide_vjp: unsupported flags 0x%x", flags); return DGFS_EINVAL; }
+  if (!pl->vhs) { set_error("dgfs_collide_vjp: only VHS plans (alpha = 1) have an adjoint in this build"); return DGFS_EUNSUPPORTED; }
   if (n_nodes == 0) return DGFS_OK;
   if (!fp || !fq || !wbar || (!grad_fp && !grad_fq)) { set_error("dgfs_collide_vjp: NULL array"); return DGFS_EINVAL; }
   const int64_t n3 = (int64_t)pl->N * pl->N * pl->N;

@@ -151,7 +151,8 @@ __global__ void __launch_bounds__(N) k_vjp_yz(VjpArgs v) {
         if (a.sidx[m] != s) continue;
         // u (row y = t) from X_uside with the yz phases of direction m
         {
-          const C<T> *src = X + (((size_t)uside * a.Nr + r) * a.Sx + s) * n3 + (size_t)jx * N * N;
+          const int rx = a.sx_zero[s] ? 0 : r;
+          const C<T> *src = X + (((size_t)uside * a.Nr + rx) * a.Sx + s) * n3 + (size_t)jx * N * N;
           const C<T> *ph = pyz + (((size_t)uside * a.Nr + r) * a.M + m) * 2 * N;
           const C<T> zph = ph[N + t];
           C<T> col[N];

@@ -363,3 +363,34 @@ class _CollideFn:
 def collide_autograd(plan, p, q, fp, fq):
     """Differentiable Q^{pq}(fp, fq) for [n_nodes, N, N, N] float64 tensors."""
     return _CollideFn.get().apply(fp, fq, plan, p, q)
+
+
+def collide_batched(plans, items, accumulate=False, ws=None, stream=None):
+    """Heterogeneous batch in one launch per pipeline stage.
+
+    plans: list of Plan (same precision); items: list of
+    (plan_index, p, q, fp, fq, out) with [n_nodes, N, N, N] float64 CUDA
+    tensors (node-strided views allowed)."""
+    torch = _torch()
+    handles = (ct.c_void_p * len(plans))(*[pl.handle for pl in plans])
+    arr = (Item * max(len(items), 1))()
+    for i, (k, p, q, fp, fq, out) in enumerate(items):
+        N = plans[k].N
+        if fp.dim() == 3:
+            fp, fq, out = fp[None], fq[None], out[None]
+        pf, sf = _node_view(fp, N)
+        pq_, sq = _node_view(fq, N)
+        po, so = _node_view(out, N)
+        if fp.shape[0] > 1 and sf != sq:
+            raise ValueError("item %d: fp and fq must share the node stride" % i)
+        arr[i] = Item(k, p, q, fp.shape[0], pf, pq_, sf, po, so)
+    n = len(items)
+    if ws is None:
+        nb = lib.dgfs_batched_workspace_bytes(handles, len(plans), arr, n)
+        if nb == 0 and n:
+            raise DGFSError(EINVAL, "dgfs_batched_workspace_bytes")
+        ws = torch.empty(max(nb, 256), dtype=torch.uint8, device="cuda")
+    _check(lib.dgfs_collide_batched(handles, len(plans), arr, n, ACCUMULATE if accumulate else 0,
+                                    ct.c_void_p(ws.data_ptr()), ws.numel(), _stream_ptr(stream)),
+           "dgfs_collide_batched")
+    return ws
