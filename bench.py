@@ -37,7 +37,23 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 256 MiB device copy (reference for HBM byte counters)")
     return ap.parse_args()
+
+
+def copy_calibration():
+    """A plain device-to-device copy of 256 MiB, 5 times: the per-dispatch
+    FETCH_SIZE / WRITE_SIZE it shows under rocprofv3 --pmc calibrate the
+    counters (expected 262144 KiB each)."""
+    import torch
+    n = 256 << 20
+    src = torch.ones(n // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(5):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes": n, "dispatches": 5}))
 
 
 def gain_yz_model(N, M, Nr, Sx, elt):
@@ -144,6 +160,9 @@ def cpu_baseline(seconds):
 
 def main():
     args = parse()
+    if args.copy_calibration:
+        copy_calibration()
+        return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU only: the collision hot path is benchmarked on a single "
@@ -161,10 +180,19 @@ def main():
     b, f = gain_yz_model(cfg["N"], cfg["M"], cfg["Nrho"], r64["Sx"], 8)
     achieved_gbs = b * evals_per_launch / (avg_ms / 1e3) / 1e9
     achieved_tf = f * evals_per_launch / (avg_ms / 1e3) / 1e12
-    roof = {"bound": "hbm", "achieved": round(achieved_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved_gbs / HBM_PEAK_GBS, 4), "traffic": None,
-            "kernel": name, "avg_launch_ms": round(avg_ms, 4), "evals_per_launch": evals_per_launch,
-            "fp64_tflops": round(achieved_tf, 2), "fp64_flop_frac": round(achieved_tf / FP64_PEAK_TFLOPS, 4)}
+    hbm_frac = achieved_gbs / HBM_PEAK_GBS
+    alu_frac = achieved_tf / FP64_PEAK_TFLOPS
+    if hbm_frac >= alu_frac:
+        roof = {"bound": "hbm", "achieved": round(achieved_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(hbm_frac, 4)}
+    else:
+        roof = {"bound": "alu", "achieved": round(achieved_tf, 2), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(alu_frac, 4)}
+    roof.update({"traffic": None, "kernel": name, "avg_launch_ms": round(avg_ms, 4),
+                 "evals_per_launch": evals_per_launch, "algorithmic_bytes_per_eval": b,
+                 "nominal_flops_per_eval": f, "hbm_GBps": round(achieved_gbs, 1),
+                 "hbm_frac": round(hbm_frac, 4), "fp64_tflops": round(achieved_tf, 2),
+                 "fp64_alu_frac": round(alu_frac, 4)})
     line = {
         "metric": "collision evals/s at N=32^3 (FP64; FP32-mixed beside it)",
         "value": round(value, 1),

@@ -137,7 +137,7 @@ static size_t lds_bytes(int stage, int nmax, size_t elt) {
     if (N > nmax) continue;
     const int gs = 64 / N > 0 ? 64 / N : 1, gg = 128 / (2 * N) > 0 ? 128 / (2 * N) : 1;
     const size_t plane = (size_t)N * (N + 1) * 2 * elt;
-    if (stage == kGainYZ) best = std::max(best, gg * plane);
+    if (stage == kGainYZ) best = std::max(best, gg * plane * (elt == 4 ? 2 : 1));
     else if (stage == kFwd || stage == kFinal) best = std::max(best, gs * plane);
   }
   return best;
@@ -292,6 +292,7 @@ extern "C" dgfs_status dgfs_collide_batched(const dgfs_plan *plans, int32_t n_pl
       si.a.pair_id[0] = it.p * pl->ns + it.q;
       si.a.zp[0] = 0;
       si.a.zq[0] = nz == 1 ? 0 : 1;
+      si.a.xshare[0] = nz == 1 ? 1 : 0;
       si.fw.src[0] = it.fp + r.n0 * it.node_stride;
       si.fw.src[1] = it.fq + r.n0 * it.node_stride;
       si.fw.node_stride = it.node_stride;

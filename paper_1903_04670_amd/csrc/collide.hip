@@ -117,6 +117,8 @@ void pipeline_common(const dgfs_plan_s *pl, PipeArgs &a) {
   a.wm = pl->wm_dev;
   a.sidx = pl->sidx_dev;
   a.sx_zero = pl->sxz_dev;
+  a.morder = pl->morder_dev;
+  a.sneg = pl->sneg_dev;
 }
 
 }  // namespace dgfs
@@ -147,6 +149,7 @@ extern "C" dgfs_status dgfs_collide(dgfs_plan pl, int64_t n_nodes, int32_t p, in
   a.pair_id[0] = p * pl->ns + q;
   a.zp[0] = 0;
   a.zq[0] = nz == 1 ? 0 : 1;
+  a.xshare[0] = nz == 1 ? 1 : 0;
   for (int64_t n0 = 0; n0 < n_nodes; n0 += B) {
     const int nb = (int)std::min<int64_t>(B, n_nodes - n0);
     a.n_nodes = nb;

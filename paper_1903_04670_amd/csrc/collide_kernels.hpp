@@ -40,6 +40,9 @@ struct PipeArgs {
   const void *wm;
   const int *sidx;
   const int *sx_zero;  // [Sx]: 1 if that sigma_x value is zero (X then independent of r)
+  const int *morder;   // [M]: directions in sigma_x-group order
+  const int *sneg;     // [Sx]: index of the opposite sigma_x value, or -1
+  int xshare[kMaxPairs];  // 1: the pair has p == q on one input, so X2[s] = X1[sneg[s]]
   void *Z, *X, *Cb, *V;
 };
 
@@ -81,6 +84,20 @@ template <typename T> __device__ __forceinline__ void acc_add(T &s, T &c, T x) {
   T t = s + x;
   c += (fabs(s) >= fabs(x)) ? ((s - t) + x) : ((x - t) + s);
   s = t;
+}
+
+// Source plane of the x-shifted input of (side, r, s) for evaluation slot
+// `slot`.  With p == q on a single input, side 1 uses side 0's array of the
+// opposite x component (the phases e^{-i th s v} and e^{+i th (-s) v} agree).
+template <typename T>
+__device__ __forceinline__ const C<T> *x_plane(const PipeArgs &a, const C<T> *Xe, int slot, int side, int r,
+                                               int s, size_t n3) {
+  if (side == 1 && a.xshare[slot] && a.sneg[s] >= 0) {
+    side = 0;
+    s = a.sneg[s];
+  }
+  const int rx = a.sx_zero[s] ? 0 : r;  // X of a zero x-component does not depend on r
+  return Xe + (((size_t)side * a.Nr + rx) * a.Sx + s) * n3;
 }
 
 // ------------------------------------------------------------------ k_fwd_yz
@@ -147,8 +164,10 @@ __device__ __forceinline__ void shift_x_body(const PipeArgs &a, int bx, int side
   fft_pair<N, -1>(F, p);
   const C<T> *px = static_cast<const C<T> *>(pd.px) + (size_t)side * a.Nr * a.Sx * N;
   C<T> *X = static_cast<C<T> *>(a.X) + ((size_t)e * 2 + side) * a.Nr * a.Sx * n3;
+  const bool shared = side == 1 && a.xshare[slot];
   for (int rs = 0; rs < a.Nr * a.Sx; ++rs) {
     if (rs >= a.Sx && a.sx_zero[rs % a.Sx]) continue;
+    if (shared && a.sneg[rs % a.Sx] >= 0) continue;
     const C<T> *ph = px + (size_t)rs * N + p * H;
     C<T> w[H];
 #pragma unroll
@@ -175,9 +194,14 @@ __global__ void __launch_bounds__(64) k_shift_x(PipeArgs a) {
 // y = c back (z = 2n+p) and transforms it.  u1's row half stays in
 // registers while u2 reuses the buffer; the product is accumulated into the
 // row-half accumulator P (compensated in FP32).
+// LDS planes per group in k_gain_yz: FP32 keeps both sides' columns in
+// flight (two buffers); FP64 uses one buffer so that LDS does not limit
+// occupancy below what its registers allow.
+template <typename T> constexpr int gain_bufs() { return sizeof(T) == 4 ? 2 : 1; }
+
 template <typename T, int N, int G>
 __device__ __forceinline__ void gain_yz_body(const PipeArgs &a, int jx, int r, int e, int tid, C<T> (*lds)[N][N + 1]) {
-  constexpr int H = N / 2;
+  constexpr int H = N / 2, NB = gain_bufs<T>();
   const int g = tid / (2 * N), l = tid % (2 * N);
   const int c = l >> 1, p = l & 1;  // column (then row) index, lane parity
   const bool in_group = g < G;       // threads beyond G groups only join the barriers
@@ -195,52 +219,79 @@ __device__ __forceinline__ void gain_yz_body(const PipeArgs &a, int jx, int r, i
 #pragma unroll
     for (int k = 0; k < H; ++k) Pcx[k] = Pcy[k] = 0;
   }
+  // column pass of one side: rows y = 2n + p of column z = c, phases, iFFT_y,
+  // then column c of the buffer
+  auto col_pass = [&](int side, int m, int s, C<T>(*buf)[N + 1]) {
+    const C<T> *src = x_plane(a, X, slot, side, r, s, n3) + (size_t)jx * N * N;
+    const C<T> *ph = pyz + (((size_t)side * a.Nr + r) * a.M + m) * 2 * N;
+    const C<T> zph = ph[N + c];
+    C<T> h[H];
+#pragma unroll
+    for (int n = 0; n < H; ++n) h[n] = src[(2 * n + p) * N + c];
+#pragma unroll
+    for (int n = 0; n < H; ++n) h[n] = cmul(h[n], cmul(ph[2 * n + p], zph));
+    fft_pair<N, +1>(h, p);
+#pragma unroll
+    for (int k = 0; k < H; ++k) buf[p * H + k][c] = h[k];
+  };
+  auto accumulate = [&](int m, const C<T> (&h)[H]) {
+    const T w = uload(wm, m);
+#pragma unroll
+    for (int k = 0; k < H; ++k) {
+      const C<T> pr = cmul(u1[k], h[k]);
+      if constexpr (sizeof(T) == 4) {
+        acc_add(P[k].x, Pcx[k], w * pr.x);
+        acc_add(P[k].y, Pcy[k], w * pr.y);
+      } else {
+        P[k].x += w * pr.x;
+        P[k].y += w * pr.y;
+      }
+    }
+  };
   const int iters = (a.M + G - 1) / G;
   for (int it = 0; it < iters; ++it) {
-    const int m = it * G + g;
-    const bool active = in_group && m < a.M;
-    const int s = active ? a.sidx[m] : 0;
-    const int rx = a.sx_zero[s] ? 0 : r;  // X of a zero x-component does not depend on r
-#pragma unroll 1
-    for (int side = 0; side < 2; ++side) {
+    const int mi = it * G + g;
+    const bool active = in_group && mi < a.M;
+    const int m = active ? a.morder[mi] : 0;
+    const int s = a.sidx[m];
+    if constexpr (NB == 2) {
       if (active) {
-        const C<T> *src = X + (((size_t)side * a.Nr + rx) * a.Sx + s) * n3 + (size_t)jx * N * N;
-        const C<T> *ph = pyz + (((size_t)side * a.Nr + r) * a.M + m) * 2 * N;
-        const C<T> zph = ph[N + c];
-        C<T> h[H];
-#pragma unroll
-        for (int n = 0; n < H; ++n) h[n] = src[(2 * n + p) * N + c];
-#pragma unroll
-        for (int n = 0; n < H; ++n) h[n] = cmul(h[n], cmul(ph[2 * n + p], zph));
-        fft_pair<N, +1>(h, p);
-#pragma unroll
-        for (int k = 0; k < H; ++k) lds[g][p * H + k][c] = h[k];
+        col_pass(0, m, s, lds[2 * g]);
+        col_pass(1, m, s, lds[2 * g + 1]);
       }
       __syncthreads();
       if (active) {
         C<T> h[H];
 #pragma unroll
-        for (int n = 0; n < H; ++n) h[n] = lds[g][c][2 * n + p];
+        for (int n = 0; n < H; ++n) h[n] = lds[2 * g][c][2 * n + p];
         fft_pair<N, +1>(h, p);
-        if (side == 0) {
 #pragma unroll
-          for (int k = 0; k < H; ++k) u1[k] = h[k];
-        } else {
-          const T w = uload(wm, m);
+        for (int k = 0; k < H; ++k) u1[k] = h[k];
 #pragma unroll
-          for (int k = 0; k < H; ++k) {
-            const C<T> pr = cmul(u1[k], h[k]);
-            if constexpr (sizeof(T) == 4) {
-              acc_add(P[k].x, Pcx[k], w * pr.x);
-              acc_add(P[k].y, Pcy[k], w * pr.y);
-            } else {
-              P[k].x += w * pr.x;
-              P[k].y += w * pr.y;
-            }
+        for (int n = 0; n < H; ++n) h[n] = lds[2 * g + 1][c][2 * n + p];
+        fft_pair<N, +1>(h, p);
+        accumulate(m, h);
+      }
+      __syncthreads();
+    } else {
+#pragma unroll 1
+      for (int side = 0; side < 2; ++side) {
+        if (active) col_pass(side, m, s, lds[g]);
+        __syncthreads();
+        if (active) {
+          C<T> h[H];
+#pragma unroll
+          for (int n = 0; n < H; ++n) h[n] = lds[g][c][2 * n + p];
+          fft_pair<N, +1>(h, p);
+          if (side == 0) {
+#pragma unroll
+            for (int k = 0; k < H; ++k) u1[k] = h[k];
+          } else {
+            accumulate(m, h);
           }
         }
+        __syncthreads();
       }
-      __syncthreads();
     }
   }
   if constexpr (sizeof(T) == 4) {
@@ -250,7 +301,7 @@ __device__ __forceinline__ void gain_yz_body(const PipeArgs &a, int jx, int r, i
   // P (row y = c, z = p*H + k) to LDS; groups combined in group order
   if (in_group) {
 #pragma unroll
-    for (int k = 0; k < H; ++k) lds[g][c][p * H + k] = P[k];
+    for (int k = 0; k < H; ++k) lds[NB * g][c][p * H + k] = P[k];
   }
   __syncthreads();
   if (g == 0) {
@@ -260,7 +311,7 @@ __device__ __forceinline__ void gain_yz_body(const PipeArgs &a, int jx, int r, i
     for (int n = 0; n < H; ++n) {
       T sx = lds[0][c][2 * n + p].x, sy = lds[0][c][2 * n + p].y, cx = 0, cy = 0;
       for (int q = 1; q < G; ++q) {
-        const C<T> v = lds[q][c][2 * n + p];
+        const C<T> v = lds[NB * q][c][2 * n + p];
         if constexpr (sizeof(T) == 4) {
           acc_add(sx, cx, v.x);
           acc_add(sy, cy, v.y);
@@ -293,7 +344,7 @@ __device__ __forceinline__ void gain_yz_body(const PipeArgs &a, int jx, int r, i
 }
 template <typename T, int N, int G>
 __global__ void __launch_bounds__(G * 2 * N) k_gain_yz(PipeArgs a) {
-  __shared__ C<T> lds[G][N][N + 1];
+  __shared__ C<T> lds[G * gain_bufs<T>()][N][N + 1];
   gain_yz_body<T, N, G>(a, blockIdx.x, blockIdx.y, blockIdx.z, threadIdx.x, lds);
 }
 

@@ -50,6 +50,8 @@ struct dgfs_plan_s {
   const void *wm_dev = nullptr;        // [M] T sphere weights
   const int *sidx_dev = nullptr;       // [M]
   const int *sxz_dev = nullptr;        // [Sx] zero-x-component flags
+  const int *morder_dev = nullptr;     // [M] directions ordered by sigma_x group
+  const int *sneg_dev = nullptr;       // [Sx] index of -sigma_x (or -1)
   // nodal DG operators on P+1 Gauss-Lobatto points (row-major (P+1)^2)
   std::vector<double> dg_r, dg_Dr, dg_Minv;
   // (C C^T)^{-1} of the conservation constraints of all species (ns+4)^2

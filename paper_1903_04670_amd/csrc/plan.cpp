@@ -280,7 +280,7 @@ extern "C" dgfs_status dgfs_plan_create(const dgfs_params *prm, dgfs_plan *out) 
   const size_t nvals = hostbuf.size();
   const size_t bytes_vals = ((nvals * e + 255) / 256) * 256;
   const size_t bytes_pairs = ((npair * sizeof(PairDev) + 255) / 256) * 256;
-  const size_t bytes_sidx = (((M + pl->Sx) * sizeof(int) + 255) / 256) * 256;
+  const size_t bytes_sidx = (((2 * M + 2 * pl->Sx) * sizeof(int) + 255) / 256) * 256;
   pl->dev_bytes = bytes_vals + bytes_pairs + bytes_sidx;
   hipError_t he = hipMalloc(&pl->dev, pl->dev_bytes);
   if (he != hipSuccess) {
@@ -310,11 +310,24 @@ extern "C" dgfs_status dgfs_plan_create(const dgfs_params *prm, dgfs_plan *out) 
     std::vector<int> z(pl->Sx);
     for (int s = 0; s < pl->Sx; ++s) z[s] = pl->sx_val[s] == 0.0 ? 1 : 0;
     std::memcpy(img.data() + bytes_vals + bytes_pairs + M * sizeof(int), z.data(), pl->Sx * sizeof(int));
+    // directions ordered by their sigma_x group (consecutive terms share X arrays)
+    std::vector<int> order(M);
+    for (int m = 0; m < M; ++m) order[m] = m;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return pl->sx_idx[a] < pl->sx_idx[b]; });
+    std::memcpy(img.data() + bytes_vals + bytes_pairs + (M + pl->Sx) * sizeof(int), order.data(), M * sizeof(int));
+    // index of the opposite x component, if present exactly
+    std::vector<int> neg(pl->Sx, -1);
+    for (int s = 0; s < pl->Sx; ++s)
+      for (int t = 0; t < pl->Sx; ++t)
+        if (pl->sx_val[t] == -pl->sx_val[s]) neg[s] = t;
+    std::memcpy(img.data() + bytes_vals + bytes_pairs + (2 * M + pl->Sx) * sizeof(int), neg.data(), pl->Sx * sizeof(int));
   }
   pl->pair_dev = reinterpret_cast<PairDev *>(base + bytes_vals);
   pl->wm_dev = base + off_wm * e;
   pl->sidx_dev = reinterpret_cast<const int *>(base + bytes_vals + bytes_pairs);
   pl->sxz_dev = pl->sidx_dev + M;
+  pl->morder_dev = pl->sidx_dev + M + pl->Sx;
+  pl->sneg_dev = pl->sidx_dev + 2 * M + pl->Sx;
   if (!pl->vhs) {
     dgfs_status vs = build_vss_tables(pl);
     if (vs != DGFS_OK) {

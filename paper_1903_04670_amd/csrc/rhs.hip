@@ -103,7 +103,7 @@ __global__ void __launch_bounds__(256) k_dg_transport(DGArgs a) {
 }
 
 struct ProjArgs {
-  int N, nsp, accumulate;
+  int N, nsp, accumulate, nblk;  // nblk: partial-moment blocks per node
   double L;
   double mass[DGFS_MAX_SPECIES];
   double ginv[(DGFS_MAX_SPECIES + 4) * (DGFS_MAX_SPECIES + 4)];
@@ -111,57 +111,76 @@ struct ProjArgs {
   int64_t q_stride;
   double *out[DGFS_MAX_SPECIES];  // species a of node n at out[a] + n*out_stride
   int64_t out_stride;
+  double *part;      // [node][nblk][nsp+4] partial moments
 };
 
-// Q~ = Q - C^T (C C^T)^{-1} C Q per node, FP64; rows of C: mass of each
+constexpr int kProjThreads = 256;
+
+// Partial moments C Q over a slice of one node's ns*N^3 values (fixed-order
+// tree reduction, so the result is deterministic).  Rows of C: mass of each
 // species, total momentum (x, y, z) and total energy, weight h^3.
-__global__ void __launch_bounds__(256) k_project(ProjArgs a) {
-  const int node = blockIdx.x;
-  const int N = a.N, n3 = N * N * N, k = a.nsp + 4;
+__global__ void __launch_bounds__(kProjThreads) k_proj_moments(ProjArgs a) {
+  const int node = blockIdx.y, blk = blockIdx.x;
+  const int N = a.N, n3 = N * N * N, k = a.nsp + 4, total = a.nsp * n3;
   const double h = 2.0 * a.L / N, w = h * h * h;
   const double *Q = a.Q + (size_t)node * a.q_stride;
   double mom[DGFS_MAX_SPECIES + 4];
   for (int i = 0; i < k; ++i) mom[i] = 0.0;
-  for (int sp = 0; sp < a.nsp; ++sp) {
-    const double m = a.mass[sp];
-    for (int v = threadIdx.x; v < n3; v += blockDim.x) {
-      const double q = Q[(size_t)sp * n3 + v];
-      const double cx = grid_c(v / (N * N), N, a.L), cy = grid_c((v / N) % N, N, a.L), cz = grid_c(v % N, N, a.L);
-      mom[sp] += w * q;
-      mom[a.nsp + 0] += w * m * cx * q;
-      mom[a.nsp + 1] += w * m * cy * q;
-      mom[a.nsp + 2] += w * m * cz * q;
-      mom[a.nsp + 3] += w * 0.5 * m * (cx * cx + cy * cy + cz * cz) * q;
-    }
+  const int per = (total + a.nblk - 1) / a.nblk;
+  const int lo = blk * per, hi = min(total, lo + per);
+  for (int i = lo + threadIdx.x; i < hi; i += kProjThreads) {
+    const int sp = i / n3, v = i % n3;
+    const double q = Q[(size_t)sp * n3 + v], m = a.mass[sp];
+    const double cx = grid_c(v / (N * N), N, a.L), cy = grid_c((v / N) % N, N, a.L), cz = grid_c(v % N, N, a.L);
+    mom[sp] += w * q;
+    mom[a.nsp + 0] += w * m * cx * q;
+    mom[a.nsp + 1] += w * m * cy * q;
+    mom[a.nsp + 2] += w * m * cz * q;
+    mom[a.nsp + 3] += w * 0.5 * m * (cx * cx + cy * cy + cz * cz) * q;
   }
-  __shared__ double red[DGFS_MAX_SPECIES + 4][256];
-  __shared__ double lam[DGFS_MAX_SPECIES + 4];
+  __shared__ double red[DGFS_MAX_SPECIES + 4][kProjThreads];
   for (int i = 0; i < k; ++i) red[i][threadIdx.x] = mom[i];
   __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
+  for (int s = kProjThreads / 2; s > 0; s >>= 1) {
     if (threadIdx.x < s)
       for (int i = 0; i < k; ++i) red[i][threadIdx.x] += red[i][threadIdx.x + s];
     __syncthreads();
   }
-  if (threadIdx.x == 0) {
-    for (int i = 0; i < k; ++i) {
-      double l = 0.0;
-      for (int j = 0; j < k; ++j) l += a.ginv[i * k + j] * red[j][0];
-      lam[i] = l;
+  if (threadIdx.x < k) a.part[((size_t)node * a.nblk + blk) * k + threadIdx.x] = red[threadIdx.x][0];
+}
+
+// Q~ = Q - C^T (C C^T)^{-1} C Q: every block sums its node's partial moments
+// in block order, forms the multipliers and corrects a slice of the node.
+__global__ void __launch_bounds__(kProjThreads) k_proj_apply(ProjArgs a) {
+  const int node = blockIdx.y, blk = blockIdx.x;
+  const int N = a.N, n3 = N * N * N, k = a.nsp + 4, total = a.nsp * n3;
+  const double h = 2.0 * a.L / N, w = h * h * h;
+  __shared__ double lam[DGFS_MAX_SPECIES + 4];
+  if (threadIdx.x < k) {
+    double mom[DGFS_MAX_SPECIES + 4];
+    for (int j = 0; j < k; ++j) {
+      double sum = 0.0;
+      for (int b = 0; b < a.nblk; ++b) sum += a.part[((size_t)node * a.nblk + b) * k + j];
+      mom[j] = sum;
     }
+    double l = 0.0;
+    for (int j = 0; j < k; ++j) l += a.ginv[threadIdx.x * k + j] * mom[j];
+    lam[threadIdx.x] = l;
   }
   __syncthreads();
-  for (int sp = 0; sp < a.nsp; ++sp) {
+  const double *Q = a.Q + (size_t)node * a.q_stride;
+  const int per = (total + a.nblk - 1) / a.nblk;
+  const int lo = blk * per, hi = min(total, lo + per);
+  for (int i = lo + threadIdx.x; i < hi; i += kProjThreads) {
+    const int sp = i / n3, v = i % n3;
     const double m = a.mass[sp];
+    const double cx = grid_c(v / (N * N), N, a.L), cy = grid_c((v / N) % N, N, a.L), cz = grid_c(v % N, N, a.L);
+    const double corr = w * (lam[sp] + m * (lam[a.nsp] * cx + lam[a.nsp + 1] * cy + lam[a.nsp + 2] * cz) +
+                             0.5 * m * (cx * cx + cy * cy + cz * cz) * lam[a.nsp + 3]);
+    const double val = Q[(size_t)sp * n3 + v] - corr;
     double *o = a.out[sp] + (size_t)node * a.out_stride;
-    for (int v = threadIdx.x; v < n3; v += blockDim.x) {
-      const double cx = grid_c(v / (N * N), N, a.L), cy = grid_c((v / N) % N, N, a.L), cz = grid_c(v % N, N, a.L);
-      const double corr = w * (lam[sp] + m * (lam[a.nsp] * cx + lam[a.nsp + 1] * cy + lam[a.nsp + 2] * cz) +
-                               0.5 * m * (cx * cx + cy * cy + cz * cz) * lam[a.nsp + 3]);
-      const double val = Q[(size_t)sp * n3 + v] - corr;
-      if (a.accumulate) o[v] += val;
-      else o[v] = val;
-    }
+    if (a.accumulate) o[v] += val;
+    else o[v] = val;
   }
 }
 
@@ -174,10 +193,12 @@ __global__ void k_combine(double *out, const double *X, const double *Y, const d
 
 static size_t align256(size_t b) { return (b + 255) / 256 * 256; }
 
+constexpr int kProjBlocks = 32;  // partial-moment blocks per node
+
 struct RhsLayout {
-  int B;               // nodes per collision chunk
-  size_t pipe, qc, nw;  // byte sizes
-  size_t total() const { return pipe + qc + nw; }
+  int B;                      // nodes per collision chunk
+  size_t pipe, qc, nw, part;  // byte sizes
+  size_t total() const { return pipe + qc + nw + part; }
 };
 
 static RhsLayout rhs_layout(const dgfs_plan_s *pl, int64_t n_nodes) {
@@ -187,6 +208,7 @@ static RhsLayout rhs_layout(const dgfs_plan_s *pl, int64_t n_nodes) {
   l.pipe = pipeline_bytes(pl, l.B, npairs, pl->ns);
   l.qc = align256((size_t)l.B * pl->ns * pl->N * pl->N * pl->N * sizeof(double));
   l.nw = 256;
+  l.part = align256((size_t)l.B * kProjBlocks * (DGFS_MAX_SPECIES + 4) * sizeof(double));
   return l;
 }
 
@@ -227,6 +249,7 @@ static hipError_t enqueue_rhs(const dgfs_plan_s *pl, const dgfs_mesh *mesh, int6
   char *base = static_cast<char *>(ws);
   double *qc = reinterpret_cast<double *>(base + l.pipe);
   double *nw = reinterpret_cast<double *>(base + l.pipe + l.qc);
+  double *part = reinterpret_cast<double *>(base + l.pipe + l.qc + l.nw);
   const bool project = flags & DGFS_PROJECT;
   if (mesh) {
     DGArgs d{};
@@ -265,6 +288,7 @@ static hipError_t enqueue_rhs(const dgfs_plan_s *pl, const dgfs_mesh *mesh, int6
       a.pair_id[p * ns + q] = p * ns + q;
       a.zp[p * ns + q] = p;
       a.zq[p * ns + q] = q;
+      a.xshare[p * ns + q] = p == q ? 1 : 0;
     }
   const int64_t node_stride = ns * n3;
   for (int64_t n0 = 0; n0 < n_nodes; n0 += l.B) {
@@ -300,7 +324,10 @@ static hipError_t enqueue_rhs(const dgfs_plan_s *pl, const dgfs_mesh *mesh, int6
       pa.q_stride = node_stride;
       for (int p = 0; p < ns; ++p) pa.out[p] = dF + n0 * node_stride + p * n3;
       pa.out_stride = node_stride;
-      DGFS_LAUNCH("k_project", k_project, dim3(nb), dim3(256), 0, st, pa);
+      pa.nblk = kProjBlocks;
+      pa.part = part;
+      DGFS_LAUNCH("k_proj_moments", k_proj_moments, dim3(kProjBlocks, nb), dim3(kProjThreads), 0, st, pa);
+      DGFS_LAUNCH("k_proj_apply", k_proj_apply, dim3(kProjBlocks, nb), dim3(kProjThreads), 0, st, pa);
     }
   }
   return hipGetLastError();

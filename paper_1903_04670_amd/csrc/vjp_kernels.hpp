@@ -151,8 +151,7 @@ __global__ void __launch_bounds__(N) k_vjp_yz(VjpArgs v) {
         if (a.sidx[m] != s) continue;
         // u (row y = t) from X_uside with the yz phases of direction m
         {
-          const int rx = a.sx_zero[s] ? 0 : r;
-          const C<T> *src = X + (((size_t)uside * a.Nr + rx) * a.Sx + s) * n3 + (size_t)jx * N * N;
+          const C<T> *src = x_plane(a, X, e % a.n_pairs, uside, r, s, n3) + (size_t)jx * N * N;
           const C<T> *ph = pyz + (((size_t)uside * a.Nr + r) * a.M + m) * 2 * N;
           const C<T> zph = ph[N + t];
           C<T> col[N];

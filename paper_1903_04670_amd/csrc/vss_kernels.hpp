@@ -29,14 +29,14 @@ __device__ __forceinline__ void gain_yz_vss_body(const PipeArgs &a, int jx, int 
   C<T> u1[H];
   const int iters = (a.M + G - 1) / G;
   for (int it = 0; it < iters; ++it) {
-    const int m = it * G + g;
-    const bool active = g < G && m < a.M;
-    const int s = active ? a.sidx[m] : 0;
-    const int rx = a.sx_zero[s] ? 0 : r;
+    const int mi = it * G + g;
+    const bool active = g < G && mi < a.M;
+    const int m = active ? a.morder[mi] : 0;
+    const int s = a.sidx[m];
 #pragma unroll 1
     for (int side = 0; side < 2; ++side) {
       if (active) {
-        const C<T> *src = X + (((size_t)side * a.Nr + rx) * a.Sx + s) * n3 + (size_t)jx * N * N;
+        const C<T> *src = x_plane(a, X, slot, side, r, s, n3) + (size_t)jx * N * N;
         const C<T> *ph = pyz + (((size_t)side * a.Nr + r) * a.M + m) * 2 * N;
         const C<T> zph = ph[N + c];
         C<T> h[H];
@@ -58,15 +58,14 @@ __device__ __forceinline__ void gain_yz_vss_body(const PipeArgs &a, int jx, int 
 #pragma unroll
           for (int k = 0; k < H; ++k) u1[k] = h[k];
         } else {
-          // product, then the forward z transform of row c (only this lane
-          // pair touches row c)
+          // product (natural z halves), forward z transform by decimation in
+          // frequency: lane p ends with kz = 2k + p, exactly the elements of
+          // row c it read above, so no other lane's data is overwritten
 #pragma unroll
-          for (int k = 0; k < H; ++k) lds[g][c][p * H + k] = cmul(u1[k], h[k]);
+          for (int k = 0; k < H; ++k) h[k] = cmul(u1[k], h[k]);
+          fft_pair_dif<N, -1>(h, p);
 #pragma unroll
-          for (int n = 0; n < H; ++n) h[n] = lds[g][c][2 * n + p];
-          fft_pair<N, -1>(h, p);
-#pragma unroll
-          for (int k = 0; k < H; ++k) lds[g][c][p * H + k] = h[k];
+          for (int k = 0; k < H; ++k) lds[g][c][2 * k + p] = h[k];
         }
       }
       __syncthreads();

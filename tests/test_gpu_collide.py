@@ -39,8 +39,9 @@ def test_homogeneous_single_species_N16(torch_cuda):
     assert rel_linf(got[0], ref) <= TOL
 
 
-@pytest.mark.parametrize("N,kind", [(4, "octahedron"), (6, "icosahedron"), (8, "icosahedron"),
-                                    (12, "fibonacci"), (18, "octahedron"), (24, "icosahedron")])
+@pytest.mark.parametrize("N,kind", [(4, "octahedron"), (6, "icosahedron"), (6, "fibonacci"), (8, "icosahedron"),
+                                    (12, "fibonacci"), (18, "octahedron"), (24, "icosahedron"),
+                                    (36, "octahedron")])
 def test_small_sizes_all_pairs(torch_cuda, N, kind):
     cfg = small_config(N, ns=2, M_kind=kind, Nrho=3 if N < 16 else 6, seed=N, n_nodes=2)
     opl = oracle_pairs(cfg)

@@ -29,8 +29,9 @@ def vss_config(N, ns=2, kind="fibonacci", M=7, Nrho=3, seed=0, n_nodes=1, alpha=
     return cfg
 
 
-def test_vss_gain_table_matches_oracle(torch_cuda):
-    cfg = vss_config(8, ns=2, M=7)
+@pytest.mark.parametrize("N,M,alpha", [(8, 7, 1.4), (6, 5, 0.8), (8, 7, 0.8)])
+def test_vss_gain_table_matches_oracle(torch_cuda, N, M, alpha):
+    cfg = vss_config(N, ns=2, M=M, alpha=alpha)
     pl = gpu_plan(cfg)
     opl = oracle_pairs(cfg)
     for p, q in [(0, 1), (1, 0)]:
@@ -41,7 +42,10 @@ def test_vss_gain_table_matches_oracle(torch_cuda):
 
 
 @pytest.mark.parametrize("N,kind,M,alpha", [(8, "fibonacci", 7, 1.4), (12, "octahedron", 6, 1.36),
-                                            (16, "icosahedron", 12, 1.32), (6, "fibonacci", 5, 0.8)])
+                                            (16, "icosahedron", 12, 1.32), (6, "fibonacci", 5, 1.4),
+                                            (8, "fibonacci", 7, 0.8), (6, "fibonacci", 5, 0.8),
+                                            (6, "octahedron", 6, 1.4), (6, "icosahedron", 12, 1.4),
+                                            (12, "fibonacci", 5, 1.4), (4, "fibonacci", 5, 1.4)])
 def test_vss_collide_parity(torch_cuda, N, kind, M, alpha):
     from paper_1903_04670_amd import dgfs
     torch = torch_cuda
