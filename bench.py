@@ -37,6 +37,10 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--workload", default="couette", choices=["couette", "vjp", "batched", "vss"],
+                    help="couette: the headline line (default); vjp: adjoint throughput, 2 species N = 32; "
+                         "batched: 1024 uneven instances in one launch per stage vs per-instance launches; "
+                         "vss: three-species VSS N = 48, M = 32, N_rho = 24")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device copy (reference for HBM byte counters)")
     return ap.parse_args()
@@ -158,10 +162,121 @@ def cpu_baseline(seconds):
                        % (n, dt))
 
 
+def _time_cuda(fn, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps
+
+
+def bench_vjp(args):
+    """Adjoint of Q^{pq} for the two species (masses 1, 2.5), N = 32,
+    icosahedron, N_rho = 16: all four ordered pairs on 64 nodes per pass."""
+    import torch
+    from paper_1903_04670_amd import dgfs, workloads as wl
+    cfg = wl.differentiation(n_nodes=64)
+    plan = dgfs.Plan(cfg["masses"], cfg["omega"], cfg["alpha"], cfg["N"], cfg["L"], cfg["Nrho"],
+                     sphere=cfg["sphere"], M=cfg["M"], R=cfg["R"])
+    F = torch.from_numpy(cfg["F"]).cuda()
+    W = torch.from_numpy(cfg["W"][:, 0]).cuda()
+    fs = [F[:, p].contiguous() for p in range(2)]
+    gf, gq = torch.empty_like(W), torch.empty_like(W)
+    ws = dgfs.workspace(plan, 64, dgfs.OP_VJP)
+    fws = dgfs.workspace(plan, 64, dgfs.OP_COLLIDE)
+    out = torch.empty_like(W)
+
+    def vjp_pass():
+        for p in range(2):
+            for q in range(2):
+                dgfs.collide_vjp(plan, p, q, fs[p], fs[q], W, gf, gq, ws=ws)
+
+    def fwd_pass():
+        for p in range(2):
+            for q in range(2):
+                dgfs.collide(plan, p, q, fs[p], fs[q], out, ws=fws)
+    tv = _time_cuda(vjp_pass, args.steps, args.warmup)
+    tf = _time_cuda(fwd_pass, args.steps, args.warmup)
+    ev = 4 * 64
+    return {"metric": "adjoint (VJP) evaluations/s, 2 species N=32^3 M=12 N_rho=16 (FP64)",
+            "value": round(ev / tv, 1), "unit": "VJP evals/s", "forward_evals_per_s": round(ev / tf, 1),
+            "vjp_over_forward_time": round(tv / tf, 3), "n_gpus": 1, "steps": args.steps, "dtype": "f64",
+            "data": "synthetic", "config": {"workload": cfg["name"], "nodes": 64, "pairs": 4}}
+
+
+def bench_batched(args):
+    """1024 space-homogeneous instances of uneven size (N in {16, 24, 32},
+    1-3 species, N_rho in {8, 16}, icosahedron): every ordered pair of every
+    instance, once through dgfs_collide_batched (one launch per stage per
+    workspace chunk) and once as one dgfs_collide call per item."""
+    import torch
+    from paper_1903_04670_amd import dgfs, workloads as wl
+    insts = wl.batched_instances(n_inst=1024)
+    plans, items = [], []
+    for k, c in enumerate(insts):
+        plans.append(dgfs.Plan(c["masses"], c["omega"], c["alpha"], c["N"], c["L"], c["Nrho"],
+                               sphere=c["sphere"], M=c["M"], R=c["R"]))
+        F = torch.from_numpy(c["F"]).cuda()
+        for p in range(c["ns"]):
+            for q in range(c["ns"]):
+                items.append((k, p, q, F[:, p], F[:, q], torch.empty(F[:, p].shape, dtype=torch.float64, device="cuda")))
+    ws = dgfs.collide_batched(plans, items)
+    ws1 = torch.empty(max(pl.workspace_bytes(1) for pl in plans), dtype=torch.uint8, device="cuda")
+
+    def batched():
+        dgfs.collide_batched(plans, items, ws=ws)
+
+    def single():
+        for (k, p, q, fp, fq, out) in items:
+            dgfs.collide(plans[k], p, q, fp, fq, out, ws=ws1)
+    tb = _time_cuda(batched, args.steps, args.warmup)
+    ts = _time_cuda(single, max(1, args.steps // 2), 1)
+    return {"metric": "collision evals/s, 1024 uneven space-homogeneous instances (FP64)",
+            "value": round(len(items) / tb, 1), "unit": "collision evals/s",
+            "per_instance_launches_evals_per_s": round(len(items) / ts, 1), "evals": len(items),
+            "batched_ms": round(tb * 1e3, 3), "per_instance_ms": round(ts * 1e3, 3), "n_gpus": 1,
+            "dtype": "f64", "data": "synthetic", "config": {"workload": "1024 instances N in {16,24,32}"}}
+
+
+def bench_vss(args):
+    """Three species (masses 1, 2, 4), VSS alpha = 1.4, N = 48, Fibonacci
+    M = 32, N_rho = 24; the mixture collision term of 4 nodes (36 ordered-pair
+    evaluations) per pass, FP64 and FP32-mixed with the FP64 projection."""
+    import torch
+    from paper_1903_04670_amd import dgfs, workloads as wl
+    cfg = wl.precision_vss(n_nodes=4)
+    F = torch.from_numpy(cfg["F"]).cuda()
+    res = {}
+    for prec in ("fp64", "fp32"):
+        plan = dgfs.Plan(cfg["masses"], cfg["omega"], cfg["alpha"], cfg["N"], cfg["L"], cfg["Nrho"],
+                         sphere=cfg["sphere"], M=cfg["M"], R=cfg["R"], precision=prec)
+        ws = dgfs.workspace(plan, 4, dgfs.OP_RHS)
+        out = torch.empty_like(F)
+        t = _time_cuda(lambda: dgfs.rhs(plan, F, out=out, project=(prec == "fp32"), ws=ws),
+                       max(1, args.steps // 2), 1)
+        res[prec] = 36 / t
+        del plan, ws
+        torch.cuda.empty_cache()
+    return {"metric": "collision evals/s, 3-species VSS N=48^3 M=32 N_rho=24", "value": round(res["fp64"], 1),
+            "unit": "collision evals/s", "fp32_mixed": round(res["fp32"], 1), "n_gpus": 1, "dtype": "f64",
+            "data": "synthetic", "config": {"workload": cfg["name"], "nodes": 4, "pairs": 9}}
+
+
 def main():
     args = parse()
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.workload != "couette":
+        if args.gpus != 1:
+            print("bench.py measures one GPU only.", file=sys.stderr)
+            sys.exit(2)
+        fn = {"vjp": bench_vjp, "batched": bench_batched, "vss": bench_vss}[args.workload]
+        print(json.dumps(fn(args)), flush=True)
         return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -172,8 +287,10 @@ def main():
     r64, r32 = res["fp64"], res["fp32"]
     value = evals_per_step / (r64["ms"] / 1e3)
     # dominant kernel roofline (FP64 path)
-    name = "k_gain_yz"
+    name = "k_gain_yz2" if "k_gain_yz2" in r64["kern"] else "k_gain_yz"
     cnt, tot = r64["kern"].get(name, (0, 0.0))
+    if cnt == 0:
+        raise RuntimeError("no gain-kernel launches were recorded")
     avg_ms = tot / max(cnt, 1)
     launches_per_step = cnt / args.steps
     evals_per_launch = evals_per_step / max(launches_per_step, 1)

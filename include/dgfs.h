@@ -224,6 +224,21 @@ dgfs_status dgfs_collide_batched(const dgfs_plan *plans, int32_t n_plans,
 dgfs_status dgfs_profile_enable(int32_t on);
 int32_t dgfs_profile_read(int32_t cap, char *names, int64_t *counts, double *total_ms);
 
+/*
+ * Launch-schedule autotuning.  Times dgfs_collide on the given inputs for the
+ * candidate chunk widths (evaluations per launch: 8 .. 256, those whose
+ * workspace fits in ws_bytes) and keeps the fastest in the plan; `chosen`
+ * (host, may be NULL) receives it.  The choice is appended to a text cache
+ * (path $DGFS_TUNE_CACHE, default ~/.cache/dgfs_tune.txt) keyed by GPU
+ * architecture and plan shape, and dgfs_plan_create reads it unless
+ * DGFS_NO_TUNE_CACHE is set.  Synchronises the stream; overwrites Q; must
+ * not run concurrently with other calls on the same plan.  Query the
+ * workspace again afterwards: it depends on the chunk width.
+ */
+dgfs_status dgfs_autotune(dgfs_plan plan, int64_t n_nodes, int32_t p, int32_t q, const double *fp,
+                          const double *fq, int64_t node_stride, double *Q, int64_t out_stride,
+                          void *ws, size_t ws_bytes, void *stream, int32_t *chosen);
+
 /* Thread-local message describing the last non-OK status of this thread. */
 const char *dgfs_last_error(void);
 

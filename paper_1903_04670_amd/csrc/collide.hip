@@ -13,6 +13,15 @@
 namespace dgfs {
 
 template <int N> constexpr int groups_for() { return N >= 64 ? 1 : (64 / N > 0 ? 64 / N : 1); }
+// gain kernel schedule: 1 = k_gain_yz, 2 = k_gain_yz2, 3 = k_gain_yz2 with the
+// next column prefetched ($DGFS_GAIN_VARIANT_FP64 / _FP32)
+template <typename T> static int gain_variant() {
+  static const int v = [] {
+    const char *s = std::getenv(sizeof(T) == 8 ? "DGFS_GAIN_VARIANT_FP64" : "DGFS_GAIN_VARIANT_FP32");
+    return s ? std::atoi(s) : 1;
+  }();
+  return v;
+}
 // groups of 2N threads per k_gain_yz block: at least 128 threads per block
 template <int N> constexpr int gain_groups() { return 128 / (2 * N) > 0 ? 128 / (2 * N) : 1; }
 
@@ -29,7 +38,14 @@ static hipError_t launch_pipeline_N(const PipeArgs &a, const FwdArgs &fw, const 
   const int pb2 = (N * N + 31) / 32;  // lane pairs: 32 x-lines per 64-thread block
   DGFS_LAUNCH("k_shift_x", (k_shift_x<T, N>), dim3(pb2, 2, E), dim3(64), 0, st, a);
   constexpr int GG = gain_groups<N>();
-  if (!vss) {
+  if (!vss && gain_variant<T>() >= 2) {
+    constexpr int G2 = gain2_pairs<N>();
+    if (gain_variant<T>() == 3)
+      DGFS_LAUNCH("k_gain_yz2", (k_gain_yz2<T, N, G2, true>), dim3(N, a.Nr, E), dim3(G2 * 4 * N), 0, st, a);
+    else
+      DGFS_LAUNCH("k_gain_yz2", (k_gain_yz2<T, N, G2, false>), dim3(N, a.Nr, E), dim3(G2 * 4 * N), 0, st, a);
+    DGFS_LAUNCH("k_gain_x", (k_gain_x<T, N>), dim3(pb2, E), dim3(64), 0, st, a);
+  } else if (!vss) {
     DGFS_LAUNCH("k_gain_yz", (k_gain_yz<T, N, GG>), dim3(N, a.Nr, E), dim3(GG * 2 * N), 0, st, a);
     DGFS_LAUNCH("k_gain_x", (k_gain_x<T, N>), dim3(pb2, E), dim3(64), 0, st, a);
   } else {
@@ -79,7 +95,8 @@ int max_evals_per_chunk() {
 }
 
 int chunk_nodes(const dgfs_plan_s *pl, int64_t n_nodes, int n_pairs) {
-  int64_t b = std::max<int64_t>(1, max_evals_per_chunk() / n_pairs);
+  const int evals = pl->chunk_evals > 0 ? pl->chunk_evals : max_evals_per_chunk();
+  int64_t b = std::max<int64_t>(1, evals / n_pairs);
   // keep a chunk's intermediates within 8 GiB (the VSS path stores every (r, m) term)
   const size_t per_node = pipeline_bytes(pl, 1, n_pairs, std::min(pl->ns, 2 * n_pairs));
   const int64_t cap = std::max<int64_t>(1, (int64_t)((size_t)8 << 30) / (int64_t)per_node);

@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <vector>
 
@@ -70,6 +71,7 @@ static int wave(int j, int N) { return j < N / 2 ? j : j - N; }
 
 bool dg_setup(int P, std::vector<double> &r, std::vector<double> &Dr, std::vector<double> &Minv);
 dgfs_status build_vss_tables(dgfs_plan_s *pl);
+void load_tuned(dgfs_plan_s *pl);
 bool projection_ginv(const dgfs_plan_s *pl, const std::vector<int> &species, std::vector<double> &G);
 
 }  // namespace dgfs
@@ -346,6 +348,7 @@ extern "C" dgfs_status dgfs_plan_create(const dgfs_params *prm, dgfs_plan *out) 
     delete pl;
     return DGFS_EHIP;
   }
+  if (!std::getenv("DGFS_NO_TUNE_CACHE")) load_tuned(pl);
   *out = pl;
   return DGFS_OK;
 }

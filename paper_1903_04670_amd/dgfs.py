@@ -70,6 +70,9 @@ lib.dgfs_profile_enable.argtypes = [_i32]
 lib.dgfs_profile_enable.restype = ct.c_int
 lib.dgfs_profile_read.argtypes = [_i32, ct.c_char_p, ct.POINTER(ct.c_int64), ct.POINTER(ct.c_double)]
 lib.dgfs_profile_read.restype = _i32
+lib.dgfs_autotune.argtypes = [_vp, _i64, _i32, _i32, _vp, _vp, _i64, _vp, _i64, _vp, _sz, _vp,
+                              ct.POINTER(ct.c_int32)]
+lib.dgfs_autotune.restype = ct.c_int
 lib.dgfs_last_error.argtypes = []
 lib.dgfs_last_error.restype = ct.c_char_p
 lib.dgfs_sphere_set.argtypes = [_i32, _i32, _dp, _dp]
@@ -80,7 +83,7 @@ lib.dgfs_plan_table.restype = ct.c_int
 EXPORTED = ["dgfs_plan_create", "dgfs_plan_destroy", "dgfs_workspace_bytes", "dgfs_collide",
             "dgfs_collide_vjp", "dgfs_rhs", "dgfs_step", "dgfs_batched_workspace_bytes",
             "dgfs_collide_batched", "dgfs_last_error", "dgfs_sphere_set", "dgfs_plan_table",
-            "dgfs_profile_enable", "dgfs_profile_read"]
+            "dgfs_profile_enable", "dgfs_profile_read", "dgfs_autotune"]
 
 
 def profile_enable(on=True):
@@ -394,3 +397,20 @@ def collide_batched(plans, items, accumulate=False, ws=None, stream=None):
                                     ct.c_void_p(ws.data_ptr()), ws.numel(), _stream_ptr(stream)),
            "dgfs_collide_batched")
     return ws
+
+
+def autotune(plan, p, q, fp, fq, out, ws=None, stream=None):
+    """Pick the chunk width (evaluations per launch) for this plan by timing
+    dgfs_collide on the given [n_nodes, N, N, N] inputs; returns it."""
+    torch = _torch()
+    n = fp.shape[0]
+    pf, sf = _node_view(fp, plan.N)
+    pq_, _ = _node_view(fq, plan.N)
+    po, so = _node_view(out, plan.N)
+    if ws is None:
+        # room for the widest candidate
+        ws = torch.empty(max(plan.workspace_bytes(n), 256) * 4, dtype=torch.uint8, device=fp.device)
+    chosen = ct.c_int32(0)
+    _check(lib.dgfs_autotune(plan.handle, n, p, q, pf, pq_, sf, po, so, ct.c_void_p(ws.data_ptr()), ws.numel(),
+                             _stream_ptr(stream), ct.byref(chosen)), "dgfs_autotune")
+    return int(chosen.value)

@@ -119,3 +119,24 @@ def test_fp32_mixed_error_bound(torch_cuda):
         print("fp32-mixed (%d,%d): rel to |Q| %.3e, rel to |loss| %.3e" % (p, q, err_q, err_l))
         assert err_l <= 2e-6
         assert err_q <= 5e-4
+
+
+def test_autotune_schedule(torch_cuda, tmp_path, monkeypatch):
+    """The autotuner picks one of its candidate chunk widths, stores it in the
+    cache, and the tuned plan gives bit-identical results."""
+    from paper_1903_04670_amd import dgfs
+    torch = torch_cuda
+    monkeypatch.setenv("DGFS_TUNE_CACHE", str(tmp_path / "tune.txt"))
+    cfg = small_config(12, ns=2, Nrho=4, seed=12, n_nodes=40)
+    pl = gpu_plan(cfg)
+    F = torch.from_numpy(cfg["F"]).cuda()
+    ref = dgfs.collide(pl, 0, 1, F[:, 0], F[:, 1])
+    out = torch.empty_like(ref)
+    chosen = dgfs.autotune(pl, 0, 1, F[:, 0], F[:, 1], out)
+    assert chosen in (8, 16, 32, 64, 128, 256)
+    assert (tmp_path / "tune.txt").read_text().strip().endswith("|%d" % chosen)
+    again = dgfs.collide(pl, 0, 1, F[:, 0], F[:, 1])
+    torch.cuda.synchronize()
+    assert torch.equal(again, ref)
+    pl2 = gpu_plan(cfg)  # picks the cached schedule up
+    assert torch.equal(dgfs.collide(pl2, 0, 1, F[:, 0], F[:, 1]), ref)
