@@ -77,6 +77,28 @@ def gain_yz_model(N, M, Nr, Sx, elt):
     return bytes_, flops
 
 
+def gain_schedule(cfg):
+    """(gain slots, direction terms) per node of the gain kernel in one
+    mixture right-hand side: with an antipodal sphere set (octahedron,
+    icosahedron), VHS pairs and a symmetric R, the (q, p) sums reuse (p, q)'s
+    and the (p, p) sums run over half of the set; otherwise every ordered
+    pair sums over all M directions."""
+    ns, M = cfg["ns"], cfg["M"]
+    R = np.asarray(cfg["R"])
+    sym = (cfg["sphere"] in ("octahedron", "icosahedron") and np.all(np.asarray(cfg["alpha"]) == 1.0)
+           and np.array_equal(R, R.T) and "DGFS_NO_SYMMETRY" not in os.environ)
+    if not sym:
+        return ns * ns, ns * ns * M
+    return ns * (ns + 1) // 2, ns * (ns - 1) // 2 * M + ns * (M // 2)
+
+
+def model_bytes_per_eval(N, M, Nr, elt):
+    """Model bytes of one collision evaluation: one HBM round trip of an N^3
+    complex intermediate per (r, m) term, plus three real N^3 arrays of I/O
+    (the FP64 input pair and output)."""
+    return 2 * (2 * elt) * N ** 3 * M * Nr + 3 * 8 * N ** 3
+
+
 def run(args):
     import torch
     from paper_1903_04670_amd import dgfs, workloads as wl
@@ -294,9 +316,16 @@ def main():
     avg_ms = tot / max(cnt, 1)
     launches_per_step = cnt / args.steps
     evals_per_launch = evals_per_step / max(launches_per_step, 1)
+    npairs = cfg["ns"] * cfg["ns"]
+    nodes_per_launch = evals_per_launch / npairs
+    gslots, gterms = gain_schedule(cfg)
     b, f = gain_yz_model(cfg["N"], cfg["M"], cfg["Nrho"], r64["Sx"], 8)
-    achieved_gbs = b * evals_per_launch / (avg_ms / 1e3) / 1e9
-    achieved_tf = f * evals_per_launch / (avg_ms / 1e3) / 1e12
+    # per launch: every gain slot reads its shifted arrays and writes C_r once;
+    # flops scale with the direction terms actually summed
+    bytes_launch = b * gslots * nodes_per_launch
+    flops_launch = f * (gterms / cfg["M"]) * nodes_per_launch
+    achieved_gbs = bytes_launch / (avg_ms / 1e3) / 1e9
+    achieved_tf = flops_launch / (avg_ms / 1e3) / 1e12
     hbm_frac = achieved_gbs / HBM_PEAK_GBS
     alu_frac = achieved_tf / FP64_PEAK_TFLOPS
     if hbm_frac >= alu_frac:
@@ -306,8 +335,10 @@ def main():
         roof = {"bound": "alu", "achieved": round(achieved_tf, 2), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(alu_frac, 4)}
     roof.update({"traffic": None, "kernel": name, "avg_launch_ms": round(avg_ms, 4),
-                 "evals_per_launch": evals_per_launch, "algorithmic_bytes_per_eval": b,
-                 "nominal_flops_per_eval": f, "hbm_GBps": round(achieved_gbs, 1),
+                 "evals_per_launch": evals_per_launch, "gain_slots_per_node": gslots,
+                 "direction_terms_per_node": gterms, "algorithmic_bytes_per_launch": bytes_launch,
+                 "algorithmic_bytes_per_gain_slot": b, "nominal_flops_per_launch": flops_launch,
+                 "hbm_GBps": round(achieved_gbs, 1),
                  "hbm_frac": round(hbm_frac, 4), "fp64_tflops": round(achieved_tf, 2),
                  "fp64_alu_frac": round(alu_frac, 4)})
     line = {
@@ -332,6 +363,15 @@ def main():
         "kernels_ms_per_step": {k: round(v[1] / args.steps, 4) for k, v in sorted(r64["kern"].items())},
         "kernels_ms_per_step_fp32": {k: round(v[1] / args.steps, 4) for k, v in sorted(r32["kern"].items())},
         "roofline": roof,
+        "model_roofline": {
+            "what": "evals/s x model bytes per eval / 8 TB/s (whole path)",
+            "bytes_per_eval_fp64": model_bytes_per_eval(cfg["N"], cfg["M"], cfg["Nrho"], 8),
+            "bytes_per_eval_fp32_mixed": model_bytes_per_eval(cfg["N"], cfg["M"], cfg["Nrho"], 4),
+            "fp64_frac": round(value * model_bytes_per_eval(cfg["N"], cfg["M"], cfg["Nrho"], 8)
+                               / (HBM_PEAK_GBS * 1e9), 4),
+            "fp32_mixed_frac": round(evals_per_step / (r32["ms"] / 1e3)
+                                     * model_bytes_per_eval(cfg["N"], cfg["M"], cfg["Nrho"], 4)
+                                     / (HBM_PEAK_GBS * 1e9), 4)},
         "finite": r64["finite"] and r32["finite"],
     }
     if not args.no_cpu_baseline:

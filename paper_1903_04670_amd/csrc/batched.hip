@@ -293,6 +293,7 @@ extern "C" dgfs_status dgfs_collide_batched(const dgfs_plan *plans, int32_t n_pl
       si.a.zp[0] = 0;
       si.a.zq[0] = nz == 1 ? 0 : 1;
       si.a.xshare[0] = nz == 1 ? 1 : 0;
+      pipeline_slots(pl, si.a);
       si.fw.src[0] = it.fp + r.n0 * it.node_stride;
       si.fw.src[1] = it.fq + r.n0 * it.node_stride;
       si.fw.node_stride = it.node_stride;

@@ -29,29 +29,29 @@ template <typename T, int N>
 static hipError_t launch_pipeline_N(const PipeArgs &a, const FwdArgs &fw, const FinalArgs &fa, hipStream_t st,
                                     bool do_fwd, bool vss) {
   constexpr int G = groups_for<N>();
-  const int E = a.n_nodes * a.n_pairs;
+  const int E = a.n_nodes * a.n_pairs, EG = a.n_nodes * a.n_gslots;
   if (do_fwd) {
     const int planes = N * fw.n_nodes * fw.nz;
     DGFS_LAUNCH("k_fwd_yz", (k_fwd_yz<T, N, G>), dim3((planes + G - 1) / G), dim3(G * N), 0, st, fw);
   }
   const int pb = (N * N + 63) / 64;
   const int pb2 = (N * N + 31) / 32;  // lane pairs: 32 x-lines per 64-thread block
-  DGFS_LAUNCH("k_shift_x", (k_shift_x<T, N>), dim3(pb2, 2, E), dim3(64), 0, st, a);
+  DGFS_LAUNCH("k_shift_x", (k_shift_x<T, N>), dim3(pb2, 2, EG), dim3(64), 0, st, a);
   constexpr int GG = gain_groups<N>();
   if (!vss && gain_variant<T>() >= 2) {
     constexpr int G2 = gain2_pairs<N>();
     if (gain_variant<T>() == 3)
-      DGFS_LAUNCH("k_gain_yz2", (k_gain_yz2<T, N, G2, true>), dim3(N, a.Nr, E), dim3(G2 * 4 * N), 0, st, a);
+      DGFS_LAUNCH("k_gain_yz2", (k_gain_yz2<T, N, G2, true>), dim3(N, a.Nr, EG), dim3(G2 * 4 * N), 0, st, a);
     else
-      DGFS_LAUNCH("k_gain_yz2", (k_gain_yz2<T, N, G2, false>), dim3(N, a.Nr, E), dim3(G2 * 4 * N), 0, st, a);
+      DGFS_LAUNCH("k_gain_yz2", (k_gain_yz2<T, N, G2, false>), dim3(N, a.Nr, EG), dim3(G2 * 4 * N), 0, st, a);
     DGFS_LAUNCH("k_gain_x", (k_gain_x<T, N>), dim3(pb2, E), dim3(64), 0, st, a);
   } else if (!vss) {
-    DGFS_LAUNCH("k_gain_yz", (k_gain_yz<T, N, GG>), dim3(N, a.Nr, E), dim3(GG * 2 * N), 0, st, a);
+    DGFS_LAUNCH("k_gain_yz", (k_gain_yz<T, N, GG>), dim3(N, a.Nr, EG), dim3(GG * 2 * N), 0, st, a);
     DGFS_LAUNCH("k_gain_x", (k_gain_x<T, N>), dim3(pb2, E), dim3(64), 0, st, a);
   } else {
     constexpr int TE = N >= 48 ? 1 : 2;
     const int egroups = a.n_pairs * ((a.n_nodes + TE - 1) / TE);
-    DGFS_LAUNCH("k_gain_yz_vss", (k_gain_yz_vss<T, N, GG>), dim3(N, a.Nr, E), dim3(GG * 2 * N), 0, st, a);
+    DGFS_LAUNCH("k_gain_yz_vss", (k_gain_yz_vss<T, N, GG>), dim3(N, a.Nr, EG), dim3(GG * 2 * N), 0, st, a);
     DGFS_LAUNCH("k_gain_x_vss", (k_gain_x_vss<T, N, TE>), dim3(pb2, egroups), dim3(64), 0, st, a);
   }
   const int fplanes = N * a.n_nodes * fa.n_out;
@@ -125,6 +125,26 @@ void pipeline_carve(const dgfs_plan_s *pl, int B, int n_pairs, int nz, void *ws,
   a.V = p;
 }
 
+bool symmetry_enabled() { return std::getenv("DGFS_NO_SYMMETRY") == nullptr; }
+
+void pipeline_slots(const dgfs_plan_s *pl, PipeArgs &a) {
+  const bool share = symmetry_enabled();
+  a.Mh = (int)pl->mhalf.size();
+  a.mhalf = pl->mhalf_dev;
+  a.n_gslots = 0;
+  for (int i = 0; i < a.n_pairs; ++i) {
+    const int p = a.pair_id[i] / pl->ns, q = a.pair_id[i] % pl->ns;
+    a.csrc[i] = i;
+    a.half[i] = (share && p == q && a.xshare[i] && pl->vhs && pl->antipodal) ? 1 : 0;
+    int src = -1;
+    if (share && p != q && pl->mirror_ok(p, q))
+      for (int j = 0; j < i; ++j)
+        if (a.csrc[j] == j && a.pair_id[j] == q * pl->ns + p && a.zp[j] == a.zq[i] && a.zq[j] == a.zp[i]) src = j;
+    if (src >= 0) a.csrc[i] = src;
+    else a.gslot[a.n_gslots++] = i;
+  }
+}
+
 void pipeline_common(const dgfs_plan_s *pl, PipeArgs &a) {
   a.Nr = pl->Nr;
   a.Sx = pl->Sx;
@@ -167,6 +187,7 @@ extern "C" dgfs_status dgfs_collide(dgfs_plan pl, int64_t n_nodes, int32_t p, in
   a.zp[0] = 0;
   a.zq[0] = nz == 1 ? 0 : 1;
   a.xshare[0] = nz == 1 ? 1 : 0;
+  pipeline_slots(pl, a);
   for (int64_t n0 = 0; n0 < n_nodes; n0 += B) {
     const int nb = (int)std::min<int64_t>(B, n_nodes - n0);
     a.n_nodes = nb;

@@ -43,8 +43,23 @@ struct PipeArgs {
   const int *morder;   // [M]: directions in sigma_x-group order
   const int *sneg;     // [Sx]: index of the opposite sigma_x value, or -1
   int xshare[kMaxPairs];  // 1: the pair has p == q on one input, so X2[s] = X1[sneg[s]]
+  // Gain schedule.  The shift and gain kernels run over the n_gslots slots
+  // gslot[]; slot i takes its C_r arrays from slot csrc[i].  With a sphere set
+  // closed under sigma -> -sigma (equal weights) the m-sum of (q, p) equals
+  // that of (p, q), so (q, p) reads (p, q)'s arrays; and for p == q on one
+  // input the terms of sigma and -sigma coincide, so half[i] = 1 sums over
+  // mhalf (one direction of each antipodal pair) with doubled weights.
+  int n_gslots;
+  int gslot[kMaxPairs], csrc[kMaxPairs], half[kMaxPairs];
+  int Mh;
+  const int *mhalf;
   void *Z, *X, *Cb, *V;
 };
+
+// Evaluation index of the eg-th (node, gain slot) of a launch over gain slots.
+__device__ __forceinline__ int gain_eval(const PipeArgs &a, int eg) {
+  return (eg / a.n_gslots) * a.n_pairs + a.gslot[eg % a.n_gslots];
+}
 
 struct FwdArgs {
   const double *src[DGFS_MAX_SPECIES];  // per Z slot: block of node n at src + n*node_stride
@@ -182,7 +197,7 @@ __device__ __forceinline__ void shift_x_body(const PipeArgs &a, int bx, int side
 }
 template <typename T, int N>
 __global__ void __launch_bounds__(64) k_shift_x(PipeArgs a) {
-  shift_x_body<T, N>(a, blockIdx.x, blockIdx.y, blockIdx.z, threadIdx.x);
+  shift_x_body<T, N>(a, blockIdx.x, blockIdx.y, gain_eval(a, blockIdx.z), threadIdx.x);
 }
 
 // ------------------------------------------------------------------ k_gain_yz
@@ -234,8 +249,9 @@ __device__ __forceinline__ void gain_yz_body(const PipeArgs &a, int jx, int r, i
 #pragma unroll
     for (int k = 0; k < H; ++k) buf[p * H + k][c] = h[k];
   };
+  const T wscale = a.half[slot] ? (T)2 : (T)1;
   auto accumulate = [&](int m, const C<T> (&h)[H]) {
-    const T w = uload(wm, m);
+    const T w = uload(wm, m) * wscale;
 #pragma unroll
     for (int k = 0; k < H; ++k) {
       const C<T> pr = cmul(u1[k], h[k]);
@@ -248,11 +264,13 @@ __device__ __forceinline__ void gain_yz_body(const PipeArgs &a, int jx, int r, i
       }
     }
   };
-  const int iters = (a.M + G - 1) / G;
+  const int Mx = a.half[slot] ? a.Mh : a.M;
+  const int *mo = a.half[slot] ? a.mhalf : a.morder;
+  const int iters = (Mx + G - 1) / G;
   for (int it = 0; it < iters; ++it) {
     const int mi = it * G + g;
-    const bool active = in_group && mi < a.M;
-    const int m = active ? a.morder[mi] : 0;
+    const bool active = in_group && mi < Mx;
+    const int m = active ? mo[mi] : 0;
     const int s = a.sidx[m];
     if constexpr (NB == 2) {
       if (active) {
@@ -345,7 +363,7 @@ __device__ __forceinline__ void gain_yz_body(const PipeArgs &a, int jx, int r, i
 template <typename T, int N, int G>
 __global__ void __launch_bounds__(G * 2 * N) k_gain_yz(PipeArgs a) {
   __shared__ C<T> lds[G * gain_bufs<T>()][N][N + 1];
-  gain_yz_body<T, N, G>(a, blockIdx.x, blockIdx.y, blockIdx.z, threadIdx.x, lds);
+  gain_yz_body<T, N, G>(a, blockIdx.x, blockIdx.y, gain_eval(a, blockIdx.z), threadIdx.x, lds);
 }
 
 // ------------------------------------------------------------------ k_gain_yz2
@@ -379,18 +397,21 @@ __device__ __forceinline__ void gain_yz2_body(const PipeArgs &a, int jx, int r, 
 #pragma unroll
     for (int k = 0; k < H; ++k) Pcx[k] = Pcy[k] = 0;
   }
+  const int Mx = a.half[slot] ? a.Mh : a.M;
+  const int *mo = a.half[slot] ? a.mhalf : a.morder;
+  const T wscale = a.half[slot] ? (T)2 : (T)1;
   auto load_col = [&](int mi) {
-    const int m = a.morder[mi];
+    const int m = mo[mi];
     const C<T> *src = x_plane(a, X, slot, side, r, a.sidx[m], n3) + (size_t)jx * N * N;
 #pragma unroll
     for (int n = 0; n < H; ++n) raw[n] = src[(2 * n + p) * N + c];
   };
-  if (PF && in_pair && g2 < a.M) load_col(g2);
-  const int iters = (a.M + G2 - 1) / G2;
+  if (PF && in_pair && g2 < Mx) load_col(g2);
+  const int iters = (Mx + G2 - 1) / G2;
   for (int it = 0; it < iters; ++it) {
     const int mi = it * G2 + g2;
-    const bool active = in_pair && mi < a.M;
-    const int m = active ? a.morder[mi] : 0;
+    const bool active = in_pair && mi < Mx;
+    const int m = active ? mo[mi] : 0;
     if (active) {
       if (!PF) load_col(mi);
       const C<T> *ph = pyz + (((size_t)side * a.Nr + r) * a.M + m) * 2 * N;
@@ -398,7 +419,7 @@ __device__ __forceinline__ void gain_yz2_body(const PipeArgs &a, int jx, int r, 
       C<T> h[H];
 #pragma unroll
       for (int n = 0; n < H; ++n) h[n] = cmul(raw[n], cmul(ph[2 * n + p], zph));
-      if (PF && mi + G2 < a.M) load_col(mi + G2);  // next direction's column, in flight during this term
+      if (PF && mi + G2 < Mx) load_col(mi + G2);  // next direction's column, in flight during this term
       fft_pair<N, +1>(h, p);
 #pragma unroll
       for (int k = 0; k < H; ++k) own[p * H + k][c] = h[k];
@@ -416,7 +437,7 @@ __device__ __forceinline__ void gain_yz2_body(const PipeArgs &a, int jx, int r, 
     }
     __syncthreads();
     if (active && side == 1) {
-      const T w = uload(wm, m);
+      const T w = uload(wm, m) * wscale;
 #pragma unroll
       for (int k = 0; k < H; ++k) {
         const C<T> pr = cmul(ubuf[c][2 * k + p], h[k]);
@@ -483,7 +504,7 @@ template <int N> constexpr int gain2_pairs() { return 128 / (4 * N) > 0 ? 128 / 
 template <typename T, int N, int G2, bool PF>
 __global__ void __launch_bounds__(G2 * 4 * N) k_gain_yz2(PipeArgs a) {
   __shared__ C<T> lds[2 * G2][N][N + 1];
-  gain_yz2_body<T, N, G2, PF>(a, blockIdx.x, blockIdx.y, blockIdx.z, threadIdx.x, lds);
+  gain_yz2_body<T, N, G2, PF>(a, blockIdx.x, blockIdx.y, gain_eval(a, blockIdx.z), threadIdx.x, lds);
 }
 
 // ------------------------------------------------------------------ k_gain_x
@@ -502,7 +523,7 @@ __device__ __forceinline__ void gain_x_body(const PipeArgs &a, int bx, int e, in
   const int vy = wave_idx(pc / N, N), vz = wave_idx(pc % N, N);
   const int kyz = vy * vy + vz * vz;
   const T *gt = static_cast<const T *>(pd.gtab);
-  const C<T> *Cb = static_cast<const C<T> *>(a.Cb) + (size_t)e * a.Nr * n3;
+  const C<T> *Cb = static_cast<const C<T> *>(a.Cb) + (size_t)(node * a.n_pairs + a.csrc[slot]) * a.Nr * n3;
   C<T> Q[H];
   T Qcx[sizeof(T) == 4 ? H : 1], Qcy[sizeof(T) == 4 ? H : 1];
 #pragma unroll

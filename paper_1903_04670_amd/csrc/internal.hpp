@@ -53,6 +53,15 @@ struct dgfs_plan_s {
   const int *sxz_dev = nullptr;        // [Sx] zero-x-component flags
   const int *morder_dev = nullptr;     // [M] directions ordered by sigma_x group
   const int *sneg_dev = nullptr;       // [Sx] index of -sigma_x (or -1)
+  // antipodal symmetry of the sphere set: every sigma_m has -sigma_m in the
+  // set with the same weight; mhalf holds one direction of each such pair
+  bool antipodal = false;
+  std::vector<int> mhalf;
+  const int *mhalf_dev = nullptr;      // [M/2] device copy of mhalf
+  // the m-sum of the gain product of (q, p) equals that of (p, q)
+  bool mirror_ok(int p, int q) const {
+    return vhs && antipodal && pairs[p * ns + q].R == pairs[q * ns + p].R;
+  }
   // nodal DG operators on P+1 Gauss-Lobatto points (row-major (P+1)^2)
   std::vector<double> dg_r, dg_Dr, dg_Minv;
   // (C C^T)^{-1} of the conservation constraints of all species (ns+4)^2

@@ -282,7 +282,34 @@ extern "C" dgfs_status dgfs_plan_create(const dgfs_params *prm, dgfs_plan *out) 
   const size_t nvals = hostbuf.size();
   const size_t bytes_vals = ((nvals * e + 255) / 256) * 256;
   const size_t bytes_pairs = ((npair * sizeof(PairDev) + 255) / 256) * 256;
-  const size_t bytes_sidx = (((2 * M + 2 * pl->Sx) * sizeof(int) + 255) / 256) * 256;
+  // antipodal pairs of directions with equal weights (see PipeArgs::half)
+  {
+    std::vector<int> anti(M, -1);
+    bool all = M % 2 == 0;
+    for (int m = 0; m < M && all; ++m) {
+      for (int t = 0; t < M; ++t) {
+        const double d = std::fabs(pl->sigma[3 * m] + pl->sigma[3 * t]) + std::fabs(pl->sigma[3 * m + 1] + pl->sigma[3 * t + 1]) +
+                         std::fabs(pl->sigma[3 * m + 2] + pl->sigma[3 * t + 2]);
+        if (d <= 1e-13 && std::fabs(pl->wsig[m] - pl->wsig[t]) <= 1e-14 * std::fabs(pl->wsig[m])) anti[m] = t;
+      }
+      if (anti[m] < 0) all = false;
+    }
+    pl->antipodal = all;
+    if (all) {
+      // one representative per pair, the one seen first in sigma_x-group order
+      std::vector<int> order(M);
+      for (int m = 0; m < M; ++m) order[m] = m;
+      std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return pl->sx_idx[a] < pl->sx_idx[b]; });
+      std::vector<char> taken(M, 0);
+      for (int m : order)
+        if (!taken[m]) {
+          taken[m] = taken[anti[m]] = 1;
+          pl->mhalf.push_back(m);
+        }
+    }
+  }
+  const int Mh = (int)pl->mhalf.size();
+  const size_t bytes_sidx = (((2 * M + 2 * pl->Sx + Mh) * sizeof(int) + 255) / 256) * 256;
   pl->dev_bytes = bytes_vals + bytes_pairs + bytes_sidx;
   hipError_t he = hipMalloc(&pl->dev, pl->dev_bytes);
   if (he != hipSuccess) {
@@ -323,6 +350,7 @@ extern "C" dgfs_status dgfs_plan_create(const dgfs_params *prm, dgfs_plan *out) 
       for (int t = 0; t < pl->Sx; ++t)
         if (pl->sx_val[t] == -pl->sx_val[s]) neg[s] = t;
     std::memcpy(img.data() + bytes_vals + bytes_pairs + (2 * M + pl->Sx) * sizeof(int), neg.data(), pl->Sx * sizeof(int));
+    if (Mh) std::memcpy(img.data() + bytes_vals + bytes_pairs + (2 * M + 2 * pl->Sx) * sizeof(int), pl->mhalf.data(), Mh * sizeof(int));
   }
   pl->pair_dev = reinterpret_cast<PairDev *>(base + bytes_vals);
   pl->wm_dev = base + off_wm * e;
@@ -330,6 +358,7 @@ extern "C" dgfs_status dgfs_plan_create(const dgfs_params *prm, dgfs_plan *out) 
   pl->sxz_dev = pl->sidx_dev + M;
   pl->morder_dev = pl->sidx_dev + M + pl->Sx;
   pl->sneg_dev = pl->sidx_dev + 2 * M + pl->Sx;
+  pl->mhalf_dev = Mh ? pl->sidx_dev + 2 * M + 2 * pl->Sx : nullptr;
   if (!pl->vhs) {
     dgfs_status vs = build_vss_tables(pl);
     if (vs != DGFS_OK) {

@@ -290,6 +290,7 @@ static hipError_t enqueue_rhs(const dgfs_plan_s *pl, const dgfs_mesh *mesh, int6
       a.zq[p * ns + q] = q;
       a.xshare[p * ns + q] = p == q ? 1 : 0;
     }
+  pipeline_slots(pl, a);
   const int64_t node_stride = ns * n3;
   for (int64_t n0 = 0; n0 < n_nodes; n0 += l.B) {
     const int nb = (int)std::min<int64_t>(l.B, n_nodes - n0);

@@ -109,6 +109,7 @@ extern "C" dgfs_status dgfs_collide_vjp(dgfs_plan pl, int64_t n_nodes, int32_t p
   v.a.zp[0] = 0;
   v.a.zq[0] = 1;
   v.a.xshare[0] = 0;
+  pipeline_slots(pl, v.a);
   v.f_stride = node_stride;
   v.w_stride = wbar_stride;
   v.g_stride = grad_stride;

@@ -86,7 +86,7 @@ __device__ __forceinline__ void gain_yz_vss_body(const PipeArgs &a, int jx, int 
 template <typename T, int N, int G>
 __global__ void __launch_bounds__(G * 2 * N) k_gain_yz_vss(PipeArgs a) {
   __shared__ C<T> lds[G][N][N + 1];
-  gain_yz_vss_body<T, N, G>(a, blockIdx.x, blockIdx.y, blockIdx.z, threadIdx.x, lds);
+  gain_yz_vss_body<T, N, G>(a, blockIdx.x, blockIdx.y, gain_eval(a, blockIdx.z), threadIdx.x, lds);
 }
 
 template <typename T, int N, int TE>

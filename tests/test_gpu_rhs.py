@@ -72,6 +72,29 @@ def test_couette_rhs_matches_oracle(torch_cuda):
     assert rel_linf(got - mixture_collision(oracle_pairs(cfg), cfg["F"]), tr) <= 1e-10
 
 
+@pytest.mark.parametrize("sphere", ["icosahedron", "octahedron"])
+def test_symmetric_gain_schedule_three_species(torch_cuda, sphere, monkeypatch):
+    """Mixture collision term of three species: the (q, p) gain sums reused
+    from (p, q), the (p, p) sums taken over half of the antipodal sphere set,
+    one pair with R_pq != R_qp computing both of its sums.  Against the
+    oracle, and against the schedule with the reuse turned off."""
+    from paper_1903_04670_amd import dgfs
+    torch = torch_cuda
+    cfg = small_config(8, ns=3, M_kind=sphere, Nrho=3, seed=21, n_nodes=3)
+    R = cfg["R"].copy()
+    R[0, 2] *= 0.9
+    cfg["R"] = R
+    ref = mixture_collision(oracle_pairs(cfg), cfg["F"])
+    pl = gpu_plan(cfg)
+    F = torch.from_numpy(cfg["F"]).cuda()
+    got = dgfs.rhs(pl, F).cpu().numpy()
+    assert rel_linf(got, ref) <= TOL
+    monkeypatch.setenv("DGFS_NO_SYMMETRY", "1")
+    full = dgfs.rhs(pl, F).cpu().numpy()
+    assert rel_linf(full, ref) <= TOL
+    assert rel_linf(got, full) <= 1e-13
+
+
 def test_projected_rhs_conserves(torch_cuda):
     """With DGFS_PROJECT the collision term of each node has zero mass per
     species and zero total momentum and energy (to rounding), and equals the

@@ -173,3 +173,53 @@ def test_projection_restores_invariants():
     assert np.max(np.abs(cons.project(Qt, N, L, masses) - Qt)) < 1e-13 * np.max(np.abs(Q))
     Z = cons.project(rng.standard_normal((3, N, N, N)), N, L, masses)
     assert abs(np.sum((Q - Qt) * Z)) < 1e-10 * np.sqrt(np.sum(Q ** 2) * np.sum(Z ** 2))
+
+
+@pytest.mark.parametrize("sphere", ["octahedron", "icosahedron"])
+def test_gain_sum_symmetries_of_antipodal_sphere_sets(sphere):
+    """Two exact identities of the gain sum of Algorithm 2 for a sphere set
+    closed under sigma -> -sigma with equal weights, at every radius r:
+    the m-sum of u1 * u2 of the pair (q, p) on (f^q, f^p) equals that of
+    (p, q) on (f^p, f^q), and for p == q on one input the terms of sigma and
+    -sigma coincide, so half of the set with doubled weights gives the sum.
+    The GPU schedule relies on both; here they are checked term by term on
+    the oracle's own transforms."""
+    from oracle import dft
+    from oracle.collide import phase_argument
+    N, L = 6, 4.0
+    sig, w = sphere_set(sphere)
+    rng = np.random.default_rng(11)
+    f1, f2 = rng.random((N, N, N)), rng.random((N, N, N))
+    p12 = PairPlan(N, L, 1.0, 2.5, 0.6, 1.0, 3, sig, w, R=5.0)
+    p21 = PairPlan(N, L, 2.5, 1.0, 0.6, 1.0, 3, sig, w, R=5.0)
+    p11 = PairPlan(N, L, 1.0, 1.0, 0.5, 1.0, 3, sig, w, R=5.0)
+
+    def msum(pl, f, g, r, ms, scale=1.0):
+        F, G = dft.fft3(f), dft.fft3(g)
+        acc = np.zeros((N, N, N), complex)
+        for m in ms:
+            a = phase_argument(pl, r, m)
+            u1 = dft.ifft3(np.exp(1j * pl.mq / (pl.mp + pl.mq) * a) * F)
+            u2 = dft.ifft3(np.exp(-1j * pl.mp / (pl.mp + pl.mq) * a) * G)
+            acc += scale * pl.w_sigma[m] * u1 * u2
+        return acc
+
+    M = len(w)
+    anti = [int(np.argmin(np.abs(sig + sig[m]).sum(1))) for m in range(M)]
+    assert all(np.abs(sig[anti[m]] + sig[m]).max() < 1e-14 for m in range(M))
+    half, seen = [], set()
+    for m in range(M):
+        if m not in seen:
+            half.append(m)
+            seen |= {m, anti[m]}
+    assert len(half) == M // 2
+    for r in range(3):
+        a = msum(p12, f1, f2, r, range(M))
+        b = msum(p21, f2, f1, r, range(M))
+        assert np.abs(a - b).max() <= 1e-13 * np.abs(a).max()
+        c = msum(p11, f1, f1, r, range(M))
+        d = msum(p11, f1, f1, r, half, 2.0)
+        assert np.abs(c - d).max() <= 1e-13 * np.abs(c).max()
+        # not an identity for p != q: the antipodal terms of (1, 2) differ
+        e = msum(p12, f1, f2, r, half, 2.0)
+        assert np.abs(a - e).max() > 1e-6 * np.abs(a).max()
