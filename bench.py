@@ -60,36 +60,77 @@ def copy_calibration():
     print(json.dumps({"copy_calibration_bytes": n, "dispatches": 5}))
 
 
-def gain_yz_model(N, M, Nr, Sx, elt):
-    """Algorithmic bytes and flops of k_gain_yz per collision evaluation.
+def gain_yz_model(N, M, Nr, sigma_x, elt, gslots_pp, gslots_pq):
+    """Algorithmic bytes and nominal flops of k_gain_yz per node.
 
-    Per (eval, r): reads the 2*Sx distinct shifted arrays X (N^3 complex
-    each) and writes one array C_r.  Flops (5 n log2 n per complex length-n
-    transform): for each of M directions two inverse 2-D transforms of every
-    x-plane, two phase multiplies (6 flops/point each), the complex product
-    and weighted accumulation (8 flops/point); one forward 2-D transform of
-    the sum."""
+    Bytes: every gain slot reads each distinct x-shifted array once (N^3
+    complex each) and writes its N_rho arrays C_r.  A side has one array per
+    (r, distinct sigma_x), except that a zero sigma_x gives one array for all
+    r; with p == q on one input the second side reuses the first side's
+    arrays of the opposite sigma_x.  gslots_pp / gslots_pq count the gain
+    slots per node with p == q and p != q.
+    Flops per direction term (5 n log2 n per complex length-n transform): two
+    inverse 2-D transforms of every x-plane, two phase multiplies (6 flops per
+    point each), product and weighted accumulation (8 flops per point); per
+    (slot, r) one forward 2-D transform of the sum (added by the caller)."""
     n3 = N ** 3
     sc = 2 * elt
-    bytes_ = Nr * (2 * Sx + 1) * n3 * sc
+    vals = np.unique(np.round(np.asarray(sigma_x, dtype=float), 15))
+    zero = int(np.sum(vals == 0.0))
+    per_side = Nr * (len(vals) - zero) + zero
+    unpaired = [v for v in vals if v != 0.0 and not np.any(vals == -v)]
+    side1_shared = Nr * len(unpaired)
+    arrays = gslots_pq * 2 * per_side + gslots_pp * (per_side + side1_shared)
+    bytes_ = (arrays + (gslots_pp + gslots_pq) * Nr) * n3 * sc
     t2 = 5.0 * N * N * np.log2(N * N)  # per plane
-    flops = Nr * N * (2 * M * t2 + M * (2 * 6 + 8) * N * N + t2)
-    return bytes_, flops
+    flops_term = N * (2 * t2 + (2 * 6 + 8) * N * N)
+    flops_fwd = N * t2
+    return bytes_, flops_term, flops_fwd
+
+
+TRAFFIC_PROFILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", "couette_n32_hbm_traffic.md")
+KERNEL_SOURCES = ["collide_kernels.hpp", "fft.hpp", "collide.hip"]
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 --pmc
+    summary (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None when the
+    kernel sources changed since the counters were taken."""
+    import hashlib
+    try:
+        text = open(TRAFFIC_PROFILE).read()
+    except OSError:
+        return None
+    h = hashlib.sha256()
+    csrc = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_1903_04670_amd", "csrc")
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(fh.read())
+    vals = {}
+    for line in text.splitlines():
+        if line.startswith("source_sha256:"):
+            vals["sha"] = line.split(":", 1)[1].strip()
+        elif line.startswith("traffic_bytes "):
+            k, v = line[len("traffic_bytes "):].rsplit(":", 1)
+            vals[k.strip()] = float(v)
+    if vals.get("sha") != h.hexdigest():
+        return None
+    return vals.get(kernel)
 
 
 def gain_schedule(cfg):
-    """(gain slots, direction terms) per node of the gain kernel in one
-    mixture right-hand side: with an antipodal sphere set (octahedron,
-    icosahedron), VHS pairs and a symmetric R, the (q, p) sums reuse (p, q)'s
-    and the (p, p) sums run over half of the set; otherwise every ordered
-    pair sums over all M directions."""
+    """Gain slots per node of one mixture right-hand side, split into p == q
+    and p != q, and the direction terms they sum: with an antipodal sphere set
+    (octahedron, icosahedron), VHS pairs and a symmetric R, the (q, p) sums
+    reuse (p, q)'s and the (p, p) sums run over half of the set; otherwise
+    every ordered pair sums over all M directions."""
     ns, M = cfg["ns"], cfg["M"]
     R = np.asarray(cfg["R"])
     sym = (cfg["sphere"] in ("octahedron", "icosahedron") and np.all(np.asarray(cfg["alpha"]) == 1.0)
            and np.array_equal(R, R.T) and "DGFS_NO_SYMMETRY" not in os.environ)
     if not sym:
-        return ns * ns, ns * ns * M
-    return ns * (ns + 1) // 2, ns * (ns - 1) // 2 * M + ns * (M // 2)
+        return ns, ns * (ns - 1), ns * ns * M
+    return ns, ns * (ns - 1) // 2, ns * (ns - 1) // 2 * M + ns * (M // 2)
 
 
 def model_bytes_per_eval(N, M, Nr, elt):
@@ -146,13 +187,8 @@ def run(args):
         torch.cuda.synchronize()
         ms_graph = (time.perf_counter() - t0) * 1e3 / args.steps
         out[prec] = dict(ms=ms, ms_graph=ms_graph, kern=kern, finite=finite, plan=plan,
-                         Sx=plan_sx(plan))
+                         sigma_x=plan.sigma[:, 0].copy())
     return cfg, evals_per_step, out
-
-
-def plan_sx(plan):
-    # distinct x components of the sphere set (the library shares x transforms across them)
-    return len(np.unique(np.round(plan.sigma[:, 0], 15)))
 
 
 def cpu_baseline(seconds):
@@ -318,12 +354,10 @@ def main():
     evals_per_launch = evals_per_step / max(launches_per_step, 1)
     npairs = cfg["ns"] * cfg["ns"]
     nodes_per_launch = evals_per_launch / npairs
-    gslots, gterms = gain_schedule(cfg)
-    b, f = gain_yz_model(cfg["N"], cfg["M"], cfg["Nrho"], r64["Sx"], 8)
-    # per launch: every gain slot reads its shifted arrays and writes C_r once;
-    # flops scale with the direction terms actually summed
-    bytes_launch = b * gslots * nodes_per_launch
-    flops_launch = f * (gterms / cfg["M"]) * nodes_per_launch
+    gpp, gpq, gterms = gain_schedule(cfg)
+    b, f_term, f_fwd = gain_yz_model(cfg["N"], cfg["M"], cfg["Nrho"], r64["sigma_x"], 8, gpp, gpq)
+    bytes_launch = b * nodes_per_launch
+    flops_launch = (f_term * gterms + f_fwd * (gpp + gpq)) * cfg["Nrho"] * nodes_per_launch
     achieved_gbs = bytes_launch / (avg_ms / 1e3) / 1e9
     achieved_tf = flops_launch / (avg_ms / 1e3) / 1e12
     hbm_frac = achieved_gbs / HBM_PEAK_GBS
@@ -334,10 +368,12 @@ def main():
     else:
         roof = {"bound": "alu", "achieved": round(achieved_tf, 2), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(alu_frac, 4)}
-    roof.update({"traffic": None, "kernel": name, "avg_launch_ms": round(avg_ms, 4),
-                 "evals_per_launch": evals_per_launch, "gain_slots_per_node": gslots,
+    roof.update({"traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+                 "traffic": measured_traffic("%s<double, %d, 2>" % (name, cfg["N"])), "kernel": name,
+                 "avg_launch_ms": round(avg_ms, 4),
+                 "evals_per_launch": evals_per_launch, "gain_slots_per_node": gpp + gpq,
                  "direction_terms_per_node": gterms, "algorithmic_bytes_per_launch": bytes_launch,
-                 "algorithmic_bytes_per_gain_slot": b, "nominal_flops_per_launch": flops_launch,
+                 "nominal_flops_per_launch": flops_launch,
                  "hbm_GBps": round(achieved_gbs, 1),
                  "hbm_frac": round(hbm_frac, 4), "fp64_tflops": round(achieved_tf, 2),
                  "fp64_alu_frac": round(alu_frac, 4)})
