@@ -259,10 +259,17 @@ def bench_vjp(args):
                 dgfs.collide(plan, p, q, fs[p], fs[q], out, ws=fws)
     tv = _time_cuda(vjp_pass, args.steps, args.warmup)
     tf = _time_cuda(fwd_pass, args.steps, args.warmup)
+    dgfs.profile_enable(True)
+    vjp_pass()
+    torch.cuda.synchronize()
+    kern = dgfs.profile_read()
+    dgfs.profile_enable(False)
     ev = 4 * 64
     return {"metric": "adjoint (VJP) evaluations/s, 2 species N=32^3 M=12 N_rho=16 (FP64)",
             "value": round(ev / tv, 1), "unit": "VJP evals/s", "forward_evals_per_s": round(ev / tf, 1),
-            "vjp_over_forward_time": round(tv / tf, 3), "n_gpus": 1, "steps": args.steps, "dtype": "f64",
+            "vjp_over_forward_time": round(tv / tf, 3),
+            "kernels_ms_per_pass": {k: round(v[1], 3) for k, v in sorted(kern.items())},
+            "n_gpus": 1, "steps": args.steps, "dtype": "f64",
             "data": "synthetic", "config": {"workload": cfg["name"], "nodes": 64, "pairs": 4}}
 
 

@@ -58,6 +58,10 @@ struct dgfs_plan_s {
   bool antipodal = false;
   std::vector<int> mhalf;
   const int *mhalf_dev = nullptr;      // [M/2] device copy of mhalf
+  // term schedule of the adjoint's yz stage: [vjp_G][vjp_T] entries
+  int vjp_G = 1, vjp_T = 0;
+  std::vector<int> vjp_sched;
+  const int *vjp_sched_dev = nullptr;
   // the m-sum of the gain product of (q, p) equals that of (p, q)
   bool mirror_ok(int p, int q) const {
     return vhs && antipodal && pairs[p * ns + q].R == pairs[q * ns + p].R;

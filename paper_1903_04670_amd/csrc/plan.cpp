@@ -309,7 +309,40 @@ extern "C" dgfs_status dgfs_plan_create(const dgfs_params *prm, dgfs_plan *out) 
     }
   }
   const int Mh = (int)pl->mhalf.size();
-  const size_t bytes_sidx = (((2 * M + 2 * pl->Sx + Mh) * sizeof(int) + 255) / 256) * 256;
+  // VJP term schedule: the (sigma_x group, side) units of the adjoint's yz
+  // stage spread over the groups of a block (largest first onto the least
+  // loaded group); each group's list holds m | side << 16 | last << 17 per
+  // term (last: the unit ends, write its sum), padded with -1 to a common
+  // length so every group passes the same barriers.
+  {
+    const int G = std::max(1, 128 / (2 * N));
+    std::vector<int> cnt(pl->Sx, 0);
+    for (int m = 0; m < M; ++m) ++cnt[pl->sx_idx[m]];
+    std::vector<std::pair<int, int>> units;  // (s, side)
+    for (int s = 0; s < pl->Sx; ++s)
+      for (int side = 0; side < 2; ++side) units.push_back({s, side});
+    std::stable_sort(units.begin(), units.end(), [&](const std::pair<int, int> &a, const std::pair<int, int> &b) {
+      return cnt[a.first] > cnt[b.first];
+    });
+    std::vector<std::vector<int>> lists(G);
+    std::vector<int> load(G, 0);
+    for (const auto &u : units) {
+      const int g = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+      int left = cnt[u.first];
+      for (int m = 0; m < M; ++m)
+        if (pl->sx_idx[m] == u.first) lists[g].push_back(m | (u.second << 16) | ((--left == 0) ? 1 << 17 : 0));
+      load[g] += cnt[u.first];
+    }
+    int T = 0;
+    for (const auto &l : lists) T = std::max<int>(T, (int)l.size());
+    pl->vjp_G = G;
+    pl->vjp_T = T;
+    pl->vjp_sched.assign((size_t)G * T, -1);
+    for (int g = 0; g < G; ++g)
+      for (size_t t = 0; t < lists[g].size(); ++t) pl->vjp_sched[(size_t)g * T + t] = lists[g][t];
+  }
+  const int nsched = (int)pl->vjp_sched.size();
+  const size_t bytes_sidx = (((2 * M + 2 * pl->Sx + Mh + nsched) * sizeof(int) + 255) / 256) * 256;
   pl->dev_bytes = bytes_vals + bytes_pairs + bytes_sidx;
   hipError_t he = hipMalloc(&pl->dev, pl->dev_bytes);
   if (he != hipSuccess) {
@@ -351,6 +384,8 @@ extern "C" dgfs_status dgfs_plan_create(const dgfs_params *prm, dgfs_plan *out) 
         if (pl->sx_val[t] == -pl->sx_val[s]) neg[s] = t;
     std::memcpy(img.data() + bytes_vals + bytes_pairs + (2 * M + pl->Sx) * sizeof(int), neg.data(), pl->Sx * sizeof(int));
     if (Mh) std::memcpy(img.data() + bytes_vals + bytes_pairs + (2 * M + 2 * pl->Sx) * sizeof(int), pl->mhalf.data(), Mh * sizeof(int));
+    std::memcpy(img.data() + bytes_vals + bytes_pairs + (2 * M + 2 * pl->Sx + Mh) * sizeof(int), pl->vjp_sched.data(),
+                nsched * sizeof(int));
   }
   pl->pair_dev = reinterpret_cast<PairDev *>(base + bytes_vals);
   pl->wm_dev = base + off_wm * e;
@@ -359,6 +394,7 @@ extern "C" dgfs_status dgfs_plan_create(const dgfs_params *prm, dgfs_plan *out) 
   pl->morder_dev = pl->sidx_dev + M + pl->Sx;
   pl->sneg_dev = pl->sidx_dev + 2 * M + pl->Sx;
   pl->mhalf_dev = Mh ? pl->sidx_dev + 2 * M + 2 * pl->Sx : nullptr;
+  pl->vjp_sched_dev = pl->sidx_dev + 2 * M + 2 * pl->Sx + Mh;
   if (!pl->vhs) {
     dgfs_status vs = build_vss_tables(pl);
     if (vs != DGFS_OK) {

@@ -39,15 +39,16 @@ static hipError_t launch_vjp_N(const VjpArgs &v, const FwdArgs &fw, hipStream_t 
   constexpr int G = vgroups<N>();
   const PipeArgs &a = v.a;
   const int E = a.n_nodes * a.n_pairs;
-  const int pb = (N * N + 63) / 64;
   const int planes_f = N * fw.n_nodes * fw.nz;
   DGFS_LAUNCH("k_fwd_yz", (k_fwd_yz<T, N, G>), dim3((planes_f + G - 1) / G), dim3(G * N), 0, st, fw);
   const int planes_w = N * a.n_nodes * 2;
   DGFS_LAUNCH("k_inv_yz", (k_inv_yz<T, N, G>), dim3((planes_w + G - 1) / G), dim3(G * N), 0, st, v);
   DGFS_LAUNCH("k_shift_x", (k_shift_x<T, N>), dim3((N * N + 31) / 32, 2, E), dim3(64), 0, st, a);
-  DGFS_LAUNCH("k_vjp_v", (k_vjp_v<T, N>), dim3(pb, E), dim3(64), 0, st, v);
-  DGFS_LAUNCH("k_vjp_yz", (k_vjp_yz<T, N>), dim3(N, a.Nr, E), dim3(N), 0, st, v);
-  DGFS_LAUNCH("k_vjp_x", (k_vjp_x<T, N>), dim3(pb, E), dim3(64), 0, st, v);
+  const int pb2 = (N * N + 31) / 32;  // lane pairs: 32 x-lines per 64-thread block
+  DGFS_LAUNCH("k_vjp_v", (k_vjp_v<T, N>), dim3(pb2, E), dim3(64), 0, st, v);
+  constexpr int GV = 128 / (2 * N) > 0 ? 128 / (2 * N) : 1;  // groups per block, as the plan's VJP schedule
+  DGFS_LAUNCH("k_vjp_yz", (k_vjp_yz<T, N, GV>), dim3(N, a.Nr, E), dim3(GV * 2 * N), 0, st, v);
+  DGFS_LAUNCH("k_vjp_x", (k_vjp_x<T, N>), dim3(pb2, E), dim3(64), 0, st, v);
   const int planes_o = N * a.n_nodes;
   DGFS_LAUNCH("k_vjp_final", (k_vjp_final<T, N, G>), dim3((planes_o + G - 1) / G), dim3(G * N), 0, st, v);
   return hipGetLastError();
@@ -114,6 +115,8 @@ extern "C" dgfs_status dgfs_collide_vjp(dgfs_plan pl, int64_t n_nodes, int32_t p
   v.w_stride = wbar_stride;
   v.g_stride = grad_stride;
   v.accumulate = (flags & DGFS_ACCUMULATE) ? 1 : 0;
+  v.sched = pl->vjp_sched_dev;
+  v.sched_T = pl->vjp_T;
   for (int64_t n0 = 0; n0 < n_nodes; n0 += B) {
     const int nb = (int)std::min<int64_t>(B, n_nodes - n0);
     v.a.n_nodes = nb;

@@ -32,6 +32,8 @@ struct VjpArgs {
   double *gf, *gg;      // outputs (may be NULL), node n at + n*g_stride
   int64_t g_stride;
   int accumulate;
+  const int *sched;     // [G][sched_T] term schedule of k_vjp_yz (m | side << 16 | last << 17, or -1)
+  int sched_T;
 };
 
 // iFFT_yz of wbar and of f*wbar on plane jx of each node (rows first through
@@ -71,189 +73,219 @@ __global__ void __launch_bounds__(G * N) k_inv_yz(VjpArgs v) {
   }
 }
 
-// Vx_r = FFT_x(g_r(|k|) iFFT_x Zw) for every r; thread = x-line.
+// Vx_r = FFT_x(g_r(|k|) iFFT_x Zw) for every r.  Lane pair (pencil, p) =
+// x-line (y, z): iFFT_x of the decimated half x = 2n + p gives wave numbers
+// pH + k; after the table multiply a decimation-in-frequency FFT_x returns
+// to x = 2k + p.
 template <typename T, int N>
 __global__ void __launch_bounds__(64) k_vjp_v(VjpArgs v) {
+  constexpr int H = N / 2;
   const PipeArgs &a = v.a;
-  const int pencil = blockIdx.x * 64 + threadIdx.x;
+  const int pencil = blockIdx.x * 32 + (threadIdx.x >> 1), p = threadIdx.x & 1;
+  const bool valid = pencil < N * N;
+  const int pc = valid ? pencil : 0;  // idle lanes still take part in the lane swaps
   const int e = blockIdx.y;
-  if (pencil >= N * N) return;
   const int node = e / a.n_pairs, slot = e % a.n_pairs;
   const PairDev pd = a.pairs[a.pair_id[slot]];
   const size_t n3 = (size_t)N * N * N;
   const int K2 = 3 * (N / 2) * (N / 2) + 1;
-  const int vy = wave_idx(pencil / N, N), vz = wave_idx(pencil % N, N), kyz = vy * vy + vz * vz;
+  const int vy = wave_idx(pc / N, N), vz = wave_idx(pc % N, N), kyz = vy * vy + vz * vz;
   const C<T> *Zw = static_cast<const C<T> *>(v.Zw) + (size_t)node * 2 * n3;
-  C<T> U[N];
+  C<T> U[H];
 #pragma unroll
-  for (int x = 0; x < N; ++x) U[x] = Zw[(size_t)x * N * N + pencil];
-  fft<N, +1>(U);
+  for (int n = 0; n < H; ++n) U[n] = Zw[(size_t)(2 * n + p) * N * N + pc];
+  fft_pair<N, +1>(U, p);
   const T *gt = static_cast<const T *>(pd.gtab);
   C<T> *Vx = static_cast<C<T> *>(v.Vx) + (size_t)e * a.Nr * n3;
   for (int r = 0; r < a.Nr; ++r) {
     const T *gr = gt + (size_t)r * K2 + kyz;
-    C<T> w[N];
+    C<T> w[H];
 #pragma unroll
-    for (int x = 0; x < N; ++x) {
-      const int vx = wave_idx(x, N);
-      w[x] = cscale(U[x], gr[vx * vx]);
+    for (int k = 0; k < H; ++k) {
+      const int vx = wave_idx(p * H + k, N);
+      w[k] = cscale(U[k], gr[vx * vx]);
     }
-    fft<N, -1>(w);
+    fft_pair_dif<N, -1>(w, p);
+    if (valid) {
 #pragma unroll
-    for (int x = 0; x < N; ++x) Vx[(size_t)r * n3 + (size_t)x * N * N + pencil] = w[x];
+      for (int k = 0; k < H; ++k) Vx[(size_t)r * n3 + (size_t)(2 * k + p) * N * N + pc] = w[k];
+    }
   }
 }
 
-// Plane (e, r, jx): v = FFT_yz(Vx_r) kept in LDS; for each distinct sigma_x
-// value s and each side, accumulate Y_side[r][s] over the directions m with
-// s(m) = s.  Thread t: column z = t (y passes), row y = t (z passes).
-template <typename T, int N>
-__global__ void __launch_bounds__(N) k_vjp_yz(VjpArgs v) {
+// Plane (e, r, jx), G groups of 2N threads; every length-N pencil is split
+// over a lane pair (c, p) as in the forward gain kernel.  Each group first
+// forms v = FFT_yz(Vx_r) on the plane (row y = c, z = pH + k in registers),
+// then works through its list of terms (m, side): u from X of the other
+// side (column pass: phases, iFFT_y, to LDS; row pass: iFFT_z), the product
+// w_m u v, iFFT_z back into the same LDS slots, iFFT_y of the columns, the
+// yz phases of `side`, and accumulation; the last term of a (sigma_x group,
+// side) unit writes Y_side[r][s] for the plane.
+template <typename T, int N, int G>
+__global__ void __launch_bounds__(G * 2 * N) k_vjp_yz(VjpArgs v) {
+  constexpr int H = N / 2;
   const PipeArgs &a = v.a;
-  __shared__ C<T> vl[N][N + 1];
-  __shared__ C<T> lds[N][N + 1];
-  const int t = threadIdx.x;
+  __shared__ C<T> lds[G][N][N + 1];
+  const int tid = threadIdx.x, g = tid / (2 * N), l = tid % (2 * N);
+  const int c = l >> 1, p = l & 1;
   const int jx = blockIdx.x, r = blockIdx.y, e = blockIdx.z;
   const int slot = e % a.n_pairs;
   const PairDev pd = a.pairs[a.pair_id[slot]];
   const size_t n3 = (size_t)N * N * N;
   const T *wm = static_cast<const T *>(a.wm);
   const C<T> *pyz = static_cast<const C<T> *>(pd.pyz);
-  // v_r on this plane: column FFT_y, then row FFT_z, rows stay in vl
+  C<T>(*buf)[N + 1] = lds[g < G ? g : 0];
+  const bool in_group = g < G;
+  C<T> vr[H];
   {
     const C<T> *src = static_cast<const C<T> *>(v.Vx) + ((size_t)e * a.Nr + r) * n3 + (size_t)jx * N * N;
-    C<T> col[N];
+    C<T> h[H];
+    if (in_group) {
 #pragma unroll
-    for (int y = 0; y < N; ++y) col[y] = src[y * N + t];
-    fft<N, -1>(col);
+      for (int n = 0; n < H; ++n) h[n] = src[(2 * n + p) * N + c];
+      fft_pair<N, -1>(h, p);
 #pragma unroll
-    for (int y = 0; y < N; ++y) vl[y][t] = col[y];
+      for (int k = 0; k < H; ++k) buf[p * H + k][c] = h[k];
+    }
     __syncthreads();
-    C<T> row[N];
+    if (in_group) {
 #pragma unroll
-    for (int z = 0; z < N; ++z) row[z] = vl[t][z];
-    fft<N, -1>(row);
+      for (int n = 0; n < H; ++n) h[n] = buf[c][2 * n + p];
+      fft_pair<N, -1>(h, p);
 #pragma unroll
-    for (int z = 0; z < N; ++z) vl[t][z] = row[z];
+      for (int k = 0; k < H; ++k) vr[k] = h[k];
+    }
     __syncthreads();
   }
   const C<T> *X = static_cast<const C<T> *>(a.X) + (size_t)e * 2 * a.Nr * a.Sx * n3;
   C<T> *Y = static_cast<C<T> *>(v.Y) + (size_t)e * 2 * a.Nr * a.Sx * n3;
-  for (int s = 0; s < a.Sx; ++s) {
-    for (int side = 0; side < 2; ++side) {
-      // side 0 accumulates Y1 = sum P1yz iFFT_yz(w u2 v): needs u2 (X side 1)
-      // side 1 accumulates Y2 = sum P2yz iFFT_yz(w u1 v): needs u1 (X side 0)
-      const int uside = 1 - side;
-      C<T> acc[N];
+  C<T> acc[H];
 #pragma unroll
-      for (int y = 0; y < N; ++y) acc[y] = C<T>{0, 0};
-      for (int m = 0; m < a.M; ++m) {
-        if (a.sidx[m] != s) continue;
-        // u (row y = t) from X_uside with the yz phases of direction m
-        {
-          const C<T> *src = x_plane(a, X, e % a.n_pairs, uside, r, s, n3) + (size_t)jx * N * N;
-          const C<T> *ph = pyz + (((size_t)uside * a.Nr + r) * a.M + m) * 2 * N;
-          const C<T> zph = ph[N + t];
-          C<T> col[N];
+  for (int k = 0; k < H; ++k) acc[k] = C<T>{0, 0};
+  const int *sched = v.sched + (in_group ? g : 0) * v.sched_T;
+  for (int t = 0; t < v.sched_T; ++t) {
+    const int ent = in_group ? sched[t] : -1;
+    const bool active = ent >= 0;
+    const int m = active ? (ent & 0xffff) : 0;
+    const int side = (ent >> 16) & 1, uside = 1 - side;
+    const int s = a.sidx[m];
+    if (active) {
+      const C<T> *src = x_plane(a, X, slot, uside, r, s, n3) + (size_t)jx * N * N;
+      const C<T> *ph = pyz + (((size_t)uside * a.Nr + r) * a.M + m) * 2 * N;
+      const C<T> zph = ph[N + c];
+      C<T> h[H];
 #pragma unroll
-          for (int y = 0; y < N; ++y) col[y] = cmul(src[y * N + t], cmul(ph[y], zph));
-          fft<N, +1>(col);
+      for (int n = 0; n < H; ++n) h[n] = src[(2 * n + p) * N + c];
 #pragma unroll
-          for (int y = 0; y < N; ++y) lds[y][t] = col[y];
-        }
-        __syncthreads();
-        {
-          C<T> row[N];
-          const T w = wm[m];
+      for (int n = 0; n < H; ++n) h[n] = cmul(h[n], cmul(ph[2 * n + p], zph));
+      fft_pair<N, +1>(h, p);
 #pragma unroll
-          for (int z = 0; z < N; ++z) row[z] = lds[t][z];
-          fft<N, +1>(row);  // u row
-#pragma unroll
-          for (int z = 0; z < N; ++z) row[z] = cscale(cmul(row[z], vl[t][z]), w);
-          fft<N, +1>(row);  // iFFT_z of the product
-#pragma unroll
-          for (int z = 0; z < N; ++z) lds[t][z] = row[z];
-        }
-        __syncthreads();
-        {
-          C<T> col[N];
-#pragma unroll
-          for (int y = 0; y < N; ++y) col[y] = lds[y][t];
-          fft<N, +1>(col);
-          const C<T> *ph = pyz + (((size_t)side * a.Nr + r) * a.M + m) * 2 * N;
-          const C<T> zph = ph[N + t];
-#pragma unroll
-          for (int y = 0; y < N; ++y) acc[y] = cadd(acc[y], cmul(col[y], cmul(ph[y], zph)));
-        }
-        __syncthreads();
-      }
-      C<T> *dst = Y + (((size_t)side * a.Nr + r) * a.Sx + s) * n3 + (size_t)jx * N * N;
-#pragma unroll
-      for (int y = 0; y < N; ++y) dst[y * N + t] = acc[y];
+      for (int k = 0; k < H; ++k) buf[p * H + k][c] = h[k];
     }
+    __syncthreads();
+    if (active) {
+      C<T> h[H];
+#pragma unroll
+      for (int n = 0; n < H; ++n) h[n] = buf[c][2 * n + p];
+      fft_pair<N, +1>(h, p);  // u on row y = c, z = pH + k
+      const T w = uload(wm, m);
+#pragma unroll
+      for (int k = 0; k < H; ++k) h[k] = cscale(cmul(h[k], vr[k]), w);
+      fft_pair_dif<N, +1>(h, p);  // iFFT_z of the product: z = 2k + p
+#pragma unroll
+      for (int k = 0; k < H; ++k) buf[c][2 * k + p] = h[k];  // the slots this lane read
+    }
+    __syncthreads();
+    if (active) {
+      C<T> h[H];
+#pragma unroll
+      for (int n = 0; n < H; ++n) h[n] = buf[2 * n + p][c];
+      fft_pair<N, +1>(h, p);  // column z = c, y = pH + k
+      const C<T> *ph = pyz + (((size_t)side * a.Nr + r) * a.M + m) * 2 * N;
+      const C<T> zph = ph[N + c];
+#pragma unroll
+      for (int k = 0; k < H; ++k) acc[k] = cadd(acc[k], cmul(h[k], cmul(ph[p * H + k], zph)));
+      if ((ent >> 17) & 1) {
+        C<T> *dst = Y + (((size_t)side * a.Nr + r) * a.Sx + s) * n3 + (size_t)jx * N * N;
+#pragma unroll
+        for (int k = 0; k < H; ++k) {
+          dst[(p * H + k) * N + c] = acc[k];
+          acc[k] = C<T>{0, 0};
+        }
+      }
+    }
+    __syncthreads();
   }
 }
 
-// Thread = x-line: Hf, Hg (with the g-side loss), Vf.
+// Lane pair (pencil, p) = x-line: Hf, Hg (with the g-side loss), Vf.  The
+// inverse x transforms of the decimated halves give wave numbers pH + k, the
+// phases and tables act there, and a decimation-in-frequency transform
+// returns to x = 2k + p.
 template <typename T, int N>
 __global__ void __launch_bounds__(64) k_vjp_x(VjpArgs v) {
+  constexpr int H = N / 2;
   const PipeArgs &a = v.a;
-  const int pencil = blockIdx.x * 64 + threadIdx.x;
+  const int pencil = blockIdx.x * 32 + (threadIdx.x >> 1), p = threadIdx.x & 1;
+  const bool valid = pencil < N * N;
+  const int pc = valid ? pencil : 0;
   const int e = blockIdx.y;
-  if (pencil >= N * N) return;
   const int node = e / a.n_pairs, slot = e % a.n_pairs;
   const PairDev pd = a.pairs[a.pair_id[slot]];
   const size_t n3 = (size_t)N * N * N;
-  const int vy = wave_idx(pencil / N, N), vz = wave_idx(pencil % N, N), kyz = vy * vy + vz * vz;
+  const int vy = wave_idx(pc / N, N), vz = wave_idx(pc % N, N), kyz = vy * vy + vz * vz;
   const C<T> *Y = static_cast<const C<T> *>(v.Y) + (size_t)e * 2 * a.Nr * a.Sx * n3;
-  C<T> *H = static_cast<C<T> *>(v.H) + (size_t)e * 3 * n3;
+  C<T> *Hs = static_cast<C<T> *>(v.H) + (size_t)e * 3 * n3;
   const T *ct = static_cast<const T *>(pd.ctab) + kyz;
-#pragma unroll
   for (int side = 0; side < 2; ++side) {
     const C<T> *px = static_cast<const C<T> *>(pd.px) + (size_t)side * a.Nr * a.Sx * N;
-    C<T> G[N];
+    C<T> G[H];
 #pragma unroll
-    for (int x = 0; x < N; ++x) G[x] = C<T>{0, 0};
+    for (int k = 0; k < H; ++k) G[k] = C<T>{0, 0};
     for (int rs = 0; rs < a.Nr * a.Sx; ++rs) {
       const C<T> *src = Y + ((size_t)side * a.Nr * a.Sx + rs) * n3;
-      C<T> w[N];
+      C<T> w[H];
 #pragma unroll
-      for (int x = 0; x < N; ++x) w[x] = src[(size_t)x * N * N + pencil];
-      fft<N, +1>(w);
-      const C<T> *ph = px + (size_t)rs * N;
+      for (int n = 0; n < H; ++n) w[n] = src[(size_t)(2 * n + p) * N * N + pc];
+      fft_pair<N, +1>(w, p);
+      const C<T> *ph = px + (size_t)rs * N + p * H;
 #pragma unroll
-      for (int x = 0; x < N; ++x) G[x] = cadd(G[x], cmul(w[x], ph[x]));
+      for (int k = 0; k < H; ++k) G[k] = cadd(G[k], cmul(w[k], ph[k]));
     }
     if (side == 1) {  // minus c(|k|) iFFT_x(Zfw) / N^3
       const C<T> *Zfw = static_cast<const C<T> *>(v.Zw) + ((size_t)node * 2 + 1) * n3;
-      C<T> w[N];
+      C<T> w[H];
 #pragma unroll
-      for (int x = 0; x < N; ++x) w[x] = Zfw[(size_t)x * N * N + pencil];
-      fft<N, +1>(w);
+      for (int n = 0; n < H; ++n) w[n] = Zfw[(size_t)(2 * n + p) * N * N + pc];
+      fft_pair<N, +1>(w, p);
 #pragma unroll
-      for (int x = 0; x < N; ++x) {
-        const int vx = wave_idx(x, N);
-        G[x] = csub(G[x], cscale(w[x], ct[vx * vx]));
+      for (int k = 0; k < H; ++k) {
+        const int vx = wave_idx(p * H + k, N);
+        G[k] = csub(G[k], cscale(w[k], ct[vx * vx]));
       }
     }
-    fft<N, -1>(G);
+    fft_pair_dif<N, -1>(G, p);
+    if (valid) {
 #pragma unroll
-    for (int x = 0; x < N; ++x) H[(size_t)side * n3 + (size_t)x * N * N + pencil] = G[x];
+      for (int k = 0; k < H; ++k) Hs[(size_t)side * n3 + (size_t)(2 * k + p) * N * N + pc] = G[k];
+    }
   }
   // Vf = iFFT_x(c FFT_x Z_g) / N^3
   const C<T> *Zg = static_cast<const C<T> *>(a.Z) + ((size_t)node * a.nz + a.zq[slot]) * n3;
-  C<T> w[N];
+  C<T> w[H];
 #pragma unroll
-  for (int x = 0; x < N; ++x) w[x] = Zg[(size_t)x * N * N + pencil];
-  fft<N, -1>(w);
+  for (int n = 0; n < H; ++n) w[n] = Zg[(size_t)(2 * n + p) * N * N + pc];
+  fft_pair<N, -1>(w, p);
 #pragma unroll
-  for (int x = 0; x < N; ++x) {
-    const int vx = wave_idx(x, N);
-    w[x] = cscale(w[x], ct[vx * vx]);
+  for (int k = 0; k < H; ++k) {
+    const int vx = wave_idx(p * H + k, N);
+    w[k] = cscale(w[k], ct[vx * vx]);
   }
-  fft<N, +1>(w);
+  fft_pair_dif<N, +1>(w, p);
+  if (valid) {
 #pragma unroll
-  for (int x = 0; x < N; ++x) H[2 * n3 + (size_t)x * N * N + pencil] = w[x];
+    for (int k = 0; k < H; ++k) Hs[2 * n3 + (size_t)(2 * k + p) * N * N + pc] = w[k];
+  }
 }
 
 // Plane (e, jx): grad_f = beta (Re FFT_yz Hf - wbar Re iFFT_yz Vf),
