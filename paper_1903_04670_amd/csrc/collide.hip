@@ -14,7 +14,8 @@ namespace dgfs {
 
 template <int N> constexpr int groups_for() { return N >= 64 ? 1 : (64 / N > 0 ? 64 / N : 1); }
 // gain kernel schedule: 1 = k_gain_yz, 2 = k_gain_yz2, 3 = k_gain_yz2 with the
-// next column prefetched ($DGFS_GAIN_VARIANT_FP64 / _FP32)
+// next column prefetched, 4 = k_gain_yz with its two sides unrolled
+// ($DGFS_GAIN_VARIANT_FP64 / _FP32)
 template <typename T> static int gain_variant() {
   static const int v = [] {
     const char *s = std::getenv(sizeof(T) == 8 ? "DGFS_GAIN_VARIANT_FP64" : "DGFS_GAIN_VARIANT_FP32");
@@ -38,7 +39,7 @@ static hipError_t launch_pipeline_N(const PipeArgs &a, const FwdArgs &fw, const 
   const int pb2 = (N * N + 31) / 32;  // lane pairs: 32 x-lines per 64-thread block
   DGFS_LAUNCH("k_shift_x", (k_shift_x<T, N>), dim3(pb2, 2, EG), dim3(64), 0, st, a);
   constexpr int GG = gain_groups<N>();
-  if (!vss && gain_variant<T>() >= 2) {
+  if (!vss && (gain_variant<T>() == 2 || gain_variant<T>() == 3)) {
     constexpr int G2 = gain2_pairs<N>();
     if (gain_variant<T>() == 3)
       DGFS_LAUNCH("k_gain_yz2", (k_gain_yz2<T, N, G2, true>), dim3(N, a.Nr, EG), dim3(G2 * 4 * N), 0, st, a);
@@ -46,7 +47,10 @@ static hipError_t launch_pipeline_N(const PipeArgs &a, const FwdArgs &fw, const 
       DGFS_LAUNCH("k_gain_yz2", (k_gain_yz2<T, N, G2, false>), dim3(N, a.Nr, EG), dim3(G2 * 4 * N), 0, st, a);
     DGFS_LAUNCH("k_gain_x", (k_gain_x<T, N>), dim3(pb2, E), dim3(64), 0, st, a);
   } else if (!vss) {
-    DGFS_LAUNCH("k_gain_yz", (k_gain_yz<T, N, GG>), dim3(N, a.Nr, EG), dim3(GG * 2 * N), 0, st, a);
+    if (gain_variant<T>() == 4)
+      DGFS_LAUNCH("k_gain_yz", (k_gain_yz<T, N, GG, true>), dim3(N, a.Nr, EG), dim3(GG * 2 * N), 0, st, a);
+    else
+      DGFS_LAUNCH("k_gain_yz", (k_gain_yz<T, N, GG>), dim3(N, a.Nr, EG), dim3(GG * 2 * N), 0, st, a);
     DGFS_LAUNCH("k_gain_x", (k_gain_x<T, N>), dim3(pb2, E), dim3(64), 0, st, a);
   } else {
     constexpr int TE = N >= 48 ? 1 : 2;

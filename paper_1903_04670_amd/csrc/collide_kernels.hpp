@@ -91,6 +91,34 @@ __device__ __forceinline__ V uload(const V *p, size_t i) {
 #endif
 }
 
+// Load from device memory through a pointer the compiler cannot place
+// (read from a descriptor): as a global-address-space load, not a flat one.
+template <typename V>
+__device__ __forceinline__ V gload(const V *p, size_t i) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  using GP = const __attribute__((address_space(1))) V *;
+  return reinterpret_cast<GP>(reinterpret_cast<uintptr_t>(p))[i];
+#else
+  return p[i];
+#endif
+}
+
+// Barrier between the phases of one group of 2N threads whose LDS plane no
+// other group touches.  When groups tile wavefronts exactly (2N divides 64)
+// no hardware barrier is needed: the LDS operations of a wavefront complete
+// in issue order, and the wavefront-scope fences keep the compiler from
+// moving LDS accesses across this point.  Otherwise a group spans waves and
+// the block barrier is used (every thread of the block must reach it).
+template <int N> __device__ __forceinline__ void group_sync() {
+  if constexpr (64 % (2 * N) == 0) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  } else {
+    __syncthreads();
+  }
+}
+
 // Neumaier-compensated accumulation (used by the FP32 path).
 template <typename T> struct Acc {
   T s, c;
@@ -186,7 +214,7 @@ __device__ __forceinline__ void shift_x_body(const PipeArgs &a, int bx, int side
     const C<T> *ph = px + (size_t)rs * N + p * H;
     C<T> w[H];
 #pragma unroll
-    for (int k = 0; k < H; ++k) w[k] = cmul(F[k], ph[k]);
+    for (int k = 0; k < H; ++k) w[k] = cmul(F[k], gload(ph, k));
     fft_pair_dif<N, +1>(w, p);
     C<T> *dst = X + (size_t)rs * n3;
     if (valid) {
@@ -214,7 +242,7 @@ __global__ void __launch_bounds__(64) k_shift_x(PipeArgs a) {
 // occupancy below what its registers allow.
 template <typename T> constexpr int gain_bufs() { return sizeof(T) == 4 ? 2 : 1; }
 
-template <typename T, int N, int G>
+template <typename T, int N, int G, bool US = false>
 __device__ __forceinline__ void gain_yz_body(const PipeArgs &a, int jx, int r, int e, int tid, C<T> (*lds)[N][N + 1]) {
   constexpr int H = N / 2, NB = gain_bufs<T>();
   const int g = tid / (2 * N), l = tid % (2 * N);
@@ -239,12 +267,12 @@ __device__ __forceinline__ void gain_yz_body(const PipeArgs &a, int jx, int r, i
   auto col_pass = [&](int side, int m, int s, C<T>(*buf)[N + 1]) {
     const C<T> *src = x_plane(a, X, slot, side, r, s, n3) + (size_t)jx * N * N;
     const C<T> *ph = pyz + (((size_t)side * a.Nr + r) * a.M + m) * 2 * N;
-    const C<T> zph = ph[N + c];
+    const C<T> zph = gload(ph, N + c);
     C<T> h[H];
 #pragma unroll
     for (int n = 0; n < H; ++n) h[n] = src[(2 * n + p) * N + c];
 #pragma unroll
-    for (int n = 0; n < H; ++n) h[n] = cmul(h[n], cmul(ph[2 * n + p], zph));
+    for (int n = 0; n < H; ++n) h[n] = cmul(h[n], cmul(gload(ph, 2 * n + p), zph));
     fft_pair<N, +1>(h, p);
 #pragma unroll
     for (int k = 0; k < H; ++k) buf[p * H + k][c] = h[k];
@@ -277,7 +305,7 @@ __device__ __forceinline__ void gain_yz_body(const PipeArgs &a, int jx, int r, i
         col_pass(0, m, s, lds[2 * g]);
         col_pass(1, m, s, lds[2 * g + 1]);
       }
-      __syncthreads();
+      group_sync<N>();
       if (active) {
         C<T> h[H];
 #pragma unroll
@@ -290,12 +318,11 @@ __device__ __forceinline__ void gain_yz_body(const PipeArgs &a, int jx, int r, i
         fft_pair<N, +1>(h, p);
         accumulate(m, h);
       }
-      __syncthreads();
+      group_sync<N>();
     } else {
-#pragma unroll 1
-      for (int side = 0; side < 2; ++side) {
+      auto do_side = [&](int side) {
         if (active) col_pass(side, m, s, lds[g]);
-        __syncthreads();
+        group_sync<N>();
         if (active) {
           C<T> h[H];
 #pragma unroll
@@ -308,7 +335,14 @@ __device__ __forceinline__ void gain_yz_body(const PipeArgs &a, int jx, int r, i
             accumulate(m, h);
           }
         }
-        __syncthreads();
+        group_sync<N>();
+      };
+      if constexpr (US) {
+        do_side(0);
+        do_side(1);
+      } else {
+#pragma unroll 1
+        for (int side = 0; side < 2; ++side) do_side(side);
       }
     }
   }
@@ -360,10 +394,10 @@ __device__ __forceinline__ void gain_yz_body(const PipeArgs &a, int jx, int r, i
     for (int k = 0; k < H; ++k) dst[(p * H + k) * N + c] = h[k];
   }
 }
-template <typename T, int N, int G>
+template <typename T, int N, int G, bool US = false>
 __global__ void __launch_bounds__(G * 2 * N) k_gain_yz(PipeArgs a) {
   __shared__ C<T> lds[G * gain_bufs<T>()][N][N + 1];
-  gain_yz_body<T, N, G>(a, blockIdx.x, blockIdx.y, gain_eval(a, blockIdx.z), threadIdx.x, lds);
+  gain_yz_body<T, N, G, US>(a, blockIdx.x, blockIdx.y, gain_eval(a, blockIdx.z), threadIdx.x, lds);
 }
 
 // ------------------------------------------------------------------ k_gain_yz2
@@ -415,10 +449,10 @@ __device__ __forceinline__ void gain_yz2_body(const PipeArgs &a, int jx, int r, 
     if (active) {
       if (!PF) load_col(mi);
       const C<T> *ph = pyz + (((size_t)side * a.Nr + r) * a.M + m) * 2 * N;
-      const C<T> zph = ph[N + c];
+      const C<T> zph = gload(ph, N + c);
       C<T> h[H];
 #pragma unroll
-      for (int n = 0; n < H; ++n) h[n] = cmul(raw[n], cmul(ph[2 * n + p], zph));
+      for (int n = 0; n < H; ++n) h[n] = cmul(raw[n], cmul(gload(ph, 2 * n + p), zph));
       if (PF && mi + G2 < Mx) load_col(mi + G2);  // next direction's column, in flight during this term
       fft_pair<N, +1>(h, p);
 #pragma unroll
@@ -542,7 +576,7 @@ __device__ __forceinline__ void gain_x_body(const PipeArgs &a, int bx, int e, in
 #pragma unroll
     for (int k = 0; k < H; ++k) {
       const int vx = wave_idx(p * H + k, N);
-      const T gv = g[vx * vx];
+      const T gv = gload(g, vx * vx);
       if constexpr (sizeof(T) == 4) {
         acc_add(Q[k].x, Qcx[k], gv * w[k].x);
         acc_add(Q[k].y, Qcy[k], gv * w[k].y);
@@ -571,7 +605,7 @@ __device__ __forceinline__ void gain_x_body(const PipeArgs &a, int bx, int e, in
 #pragma unroll
   for (int k = 0; k < H; ++k) {
     const int vx = wave_idx(p * H + k, N);
-    Q[k] = cscale(Q[k], ct[vx * vx]);
+    Q[k] = cscale(Q[k], gload(ct, vx * vx));
   }
   fft_pair_dif<N, +1>(Q, p);
   if (valid) {

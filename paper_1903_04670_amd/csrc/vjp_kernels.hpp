@@ -103,7 +103,7 @@ __global__ void __launch_bounds__(64) k_vjp_v(VjpArgs v) {
 #pragma unroll
     for (int k = 0; k < H; ++k) {
       const int vx = wave_idx(p * H + k, N);
-      w[k] = cscale(U[k], gr[vx * vx]);
+      w[k] = cscale(U[k], gload(gr, vx * vx));
     }
     fft_pair_dif<N, -1>(w, p);
     if (valid) {
@@ -147,7 +147,7 @@ __global__ void __launch_bounds__(G * 2 * N) k_vjp_yz(VjpArgs v) {
 #pragma unroll
       for (int k = 0; k < H; ++k) buf[p * H + k][c] = h[k];
     }
-    __syncthreads();
+    group_sync<N>();
     if (in_group) {
 #pragma unroll
       for (int n = 0; n < H; ++n) h[n] = buf[c][2 * n + p];
@@ -155,7 +155,7 @@ __global__ void __launch_bounds__(G * 2 * N) k_vjp_yz(VjpArgs v) {
 #pragma unroll
       for (int k = 0; k < H; ++k) vr[k] = h[k];
     }
-    __syncthreads();
+    group_sync<N>();
   }
   const C<T> *X = static_cast<const C<T> *>(a.X) + (size_t)e * 2 * a.Nr * a.Sx * n3;
   C<T> *Y = static_cast<C<T> *>(v.Y) + (size_t)e * 2 * a.Nr * a.Sx * n3;
@@ -172,17 +172,17 @@ __global__ void __launch_bounds__(G * 2 * N) k_vjp_yz(VjpArgs v) {
     if (active) {
       const C<T> *src = x_plane(a, X, slot, uside, r, s, n3) + (size_t)jx * N * N;
       const C<T> *ph = pyz + (((size_t)uside * a.Nr + r) * a.M + m) * 2 * N;
-      const C<T> zph = ph[N + c];
+      const C<T> zph = gload(ph, N + c);
       C<T> h[H];
 #pragma unroll
       for (int n = 0; n < H; ++n) h[n] = src[(2 * n + p) * N + c];
 #pragma unroll
-      for (int n = 0; n < H; ++n) h[n] = cmul(h[n], cmul(ph[2 * n + p], zph));
+      for (int n = 0; n < H; ++n) h[n] = cmul(h[n], cmul(gload(ph, 2 * n + p), zph));
       fft_pair<N, +1>(h, p);
 #pragma unroll
       for (int k = 0; k < H; ++k) buf[p * H + k][c] = h[k];
     }
-    __syncthreads();
+    group_sync<N>();
     if (active) {
       C<T> h[H];
 #pragma unroll
@@ -195,16 +195,16 @@ __global__ void __launch_bounds__(G * 2 * N) k_vjp_yz(VjpArgs v) {
 #pragma unroll
       for (int k = 0; k < H; ++k) buf[c][2 * k + p] = h[k];  // the slots this lane read
     }
-    __syncthreads();
+    group_sync<N>();
     if (active) {
       C<T> h[H];
 #pragma unroll
       for (int n = 0; n < H; ++n) h[n] = buf[2 * n + p][c];
       fft_pair<N, +1>(h, p);  // column z = c, y = pH + k
       const C<T> *ph = pyz + (((size_t)side * a.Nr + r) * a.M + m) * 2 * N;
-      const C<T> zph = ph[N + c];
+      const C<T> zph = gload(ph, N + c);
 #pragma unroll
-      for (int k = 0; k < H; ++k) acc[k] = cadd(acc[k], cmul(h[k], cmul(ph[p * H + k], zph)));
+      for (int k = 0; k < H; ++k) acc[k] = cadd(acc[k], cmul(h[k], cmul(gload(ph, p * H + k), zph)));
       if ((ent >> 17) & 1) {
         C<T> *dst = Y + (((size_t)side * a.Nr + r) * a.Sx + s) * n3 + (size_t)jx * N * N;
 #pragma unroll
@@ -214,7 +214,7 @@ __global__ void __launch_bounds__(G * 2 * N) k_vjp_yz(VjpArgs v) {
         }
       }
     }
-    __syncthreads();
+    group_sync<N>();
   }
 }
 
@@ -250,7 +250,7 @@ __global__ void __launch_bounds__(64) k_vjp_x(VjpArgs v) {
       fft_pair<N, +1>(w, p);
       const C<T> *ph = px + (size_t)rs * N + p * H;
 #pragma unroll
-      for (int k = 0; k < H; ++k) G[k] = cadd(G[k], cmul(w[k], ph[k]));
+      for (int k = 0; k < H; ++k) G[k] = cadd(G[k], cmul(w[k], gload(ph, k)));
     }
     if (side == 1) {  // minus c(|k|) iFFT_x(Zfw) / N^3
       const C<T> *Zfw = static_cast<const C<T> *>(v.Zw) + ((size_t)node * 2 + 1) * n3;
@@ -261,7 +261,7 @@ __global__ void __launch_bounds__(64) k_vjp_x(VjpArgs v) {
 #pragma unroll
       for (int k = 0; k < H; ++k) {
         const int vx = wave_idx(p * H + k, N);
-        G[k] = csub(G[k], cscale(w[k], ct[vx * vx]));
+        G[k] = csub(G[k], cscale(w[k], gload(ct, vx * vx)));
       }
     }
     fft_pair_dif<N, -1>(G, p);
@@ -279,7 +279,7 @@ __global__ void __launch_bounds__(64) k_vjp_x(VjpArgs v) {
 #pragma unroll
   for (int k = 0; k < H; ++k) {
     const int vx = wave_idx(p * H + k, N);
-    w[k] = cscale(w[k], ct[vx * vx]);
+    w[k] = cscale(w[k], gload(ct, vx * vx));
   }
   fft_pair_dif<N, +1>(w, p);
   if (valid) {

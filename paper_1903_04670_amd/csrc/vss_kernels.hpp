@@ -38,17 +38,17 @@ __device__ __forceinline__ void gain_yz_vss_body(const PipeArgs &a, int jx, int 
       if (active) {
         const C<T> *src = x_plane(a, X, slot, side, r, s, n3) + (size_t)jx * N * N;
         const C<T> *ph = pyz + (((size_t)side * a.Nr + r) * a.M + m) * 2 * N;
-        const C<T> zph = ph[N + c];
+        const C<T> zph = gload(ph, N + c);
         C<T> h[H];
 #pragma unroll
         for (int n = 0; n < H; ++n) h[n] = src[(2 * n + p) * N + c];
 #pragma unroll
-        for (int n = 0; n < H; ++n) h[n] = cmul(h[n], cmul(ph[2 * n + p], zph));
+        for (int n = 0; n < H; ++n) h[n] = cmul(h[n], cmul(gload(ph, 2 * n + p), zph));
         fft_pair<N, +1>(h, p);
 #pragma unroll
         for (int k = 0; k < H; ++k) lds[g][p * H + k][c] = h[k];
       }
-      __syncthreads();
+      group_sync<N>();
       if (active) {
         C<T> h[H];
 #pragma unroll
@@ -68,7 +68,7 @@ __device__ __forceinline__ void gain_yz_vss_body(const PipeArgs &a, int jx, int 
           for (int k = 0; k < H; ++k) lds[g][c][2 * k + p] = h[k];
         }
       }
-      __syncthreads();
+      group_sync<N>();
     }
     if (active) {
       C<T> h[H];
@@ -79,7 +79,7 @@ __device__ __forceinline__ void gain_yz_vss_body(const PipeArgs &a, int jx, int 
 #pragma unroll
       for (int k = 0; k < H; ++k) dst[(p * H + k) * N + c] = h[k];
     }
-    __syncthreads();
+    group_sync<N>();
   }
 }
 
@@ -163,7 +163,7 @@ __device__ __forceinline__ void gain_x_vss_body(const PipeArgs &a, int bx, int b
 #pragma unroll
     for (int k = 0; k < H; ++k) {
       const int vx = wave_idx(p * H + k, N);
-      q[k] = cscale(q[k], ct[vx * vx]);
+      q[k] = cscale(q[k], gload(ct, vx * vx));
     }
     fft_pair_dif<N, +1>(q, p);
     if (live) {
