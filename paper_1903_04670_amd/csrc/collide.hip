@@ -14,7 +14,8 @@ namespace dgfs {
 
 template <int N> constexpr int groups_for() { return N >= 64 ? 1 : (64 / N > 0 ? 64 / N : 1); }
 // gain kernel schedule: 1 = k_gain_yz, 2 = k_gain_yz2, 3 = k_gain_yz2 with the
-// next column prefetched, 4 = k_gain_yz with its two sides unrolled
+// next column prefetched, 4 = k_gain_yz with its two sides unrolled, 5 / 6 =
+// k_gain_yz (sides looped / unrolled) with one LDS plane per group
 // ($DGFS_GAIN_VARIANT_FP64 / _FP32)
 template <typename T> static int gain_variant() {
   static const int v = [] {
@@ -49,6 +50,10 @@ static hipError_t launch_pipeline_N(const PipeArgs &a, const FwdArgs &fw, const 
   } else if (!vss) {
     if (gain_variant<T>() == 4)
       DGFS_LAUNCH("k_gain_yz", (k_gain_yz<T, N, GG, true>), dim3(N, a.Nr, EG), dim3(GG * 2 * N), 0, st, a);
+    else if (gain_variant<T>() == 5)
+      DGFS_LAUNCH("k_gain_yz", (k_gain_yz<T, N, GG, false, 1>), dim3(N, a.Nr, EG), dim3(GG * 2 * N), 0, st, a);
+    else if (gain_variant<T>() == 6)
+      DGFS_LAUNCH("k_gain_yz", (k_gain_yz<T, N, GG, true, 1>), dim3(N, a.Nr, EG), dim3(GG * 2 * N), 0, st, a);
     else
       DGFS_LAUNCH("k_gain_yz", (k_gain_yz<T, N, GG>), dim3(N, a.Nr, EG), dim3(GG * 2 * N), 0, st, a);
     DGFS_LAUNCH("k_gain_x", (k_gain_x<T, N>), dim3(pb2, E), dim3(64), 0, st, a);

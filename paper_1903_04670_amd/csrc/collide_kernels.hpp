@@ -103,6 +103,37 @@ __device__ __forceinline__ V gload(const V *p, size_t i) {
 #endif
 }
 
+// The same address in every lane of the wavefront, as a scalar value.
+template <typename V>
+__device__ __forceinline__ const V *wave_uniform(const V *ptr) {
+  const uint64_t u = reinterpret_cast<uint64_t>(ptr);
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)u);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(u >> 32));
+  return reinterpret_cast<const V *>(((uint64_t)hi << 32) | lo);
+}
+
+// y phases of a column pass, lane pair (c, p) holding rows y = 2n + p (the
+// decimated input of fft_pair): h[n] *= ph_y(2n + p) zph.  When a group is
+// exactly one wavefront (N = 32) the table row is the same in every lane, so
+// the identity ph_y(2n + p) = ph_y(2n) ph_y(1)^p (the wave numbers of rows 2n
+// and 2n + 1 differ by one, N/2 being even) turns the 16 per-lane table
+// loads into scalar loads of ph_y(2n), and only zph ph_y(1)^p is per lane.
+// Per-lane loads that each wait for the previous one are what this avoids.
+template <typename T, int N>
+__device__ __forceinline__ void apply_col_phase(cplx<T> (&h)[N / 2], const cplx<T> *ph, int c, int p) {
+  const cplx<T> zph = gload(ph, N + c);
+  if constexpr (2 * N == 64) {
+    const cplx<T> *phu = wave_uniform(ph);
+    const cplx<T> z1 = cmul(zph, uload(phu, 1));
+    const cplx<T> L{p ? z1.x : zph.x, p ? z1.y : zph.y};
+#pragma unroll
+    for (int n = 0; n < N / 2; ++n) h[n] = cmul(h[n], cmul(uload(phu, 2 * n), L));
+  } else {
+#pragma unroll
+    for (int n = 0; n < N / 2; ++n) h[n] = cmul(h[n], cmul(gload(ph, 2 * n + p), zph));
+  }
+}
+
 // Barrier between the phases of one group of 2N threads whose LDS plane no
 // other group touches.  When groups tile wavefronts exactly (2N divides 64)
 // no hardware barrier is needed: the LDS operations of a wavefront complete
@@ -242,9 +273,9 @@ __global__ void __launch_bounds__(64) k_shift_x(PipeArgs a) {
 // occupancy below what its registers allow.
 template <typename T> constexpr int gain_bufs() { return sizeof(T) == 4 ? 2 : 1; }
 
-template <typename T, int N, int G, bool US = false>
+template <typename T, int N, int G, bool US = false, int NB = gain_bufs<T>()>
 __device__ __forceinline__ void gain_yz_body(const PipeArgs &a, int jx, int r, int e, int tid, C<T> (*lds)[N][N + 1]) {
-  constexpr int H = N / 2, NB = gain_bufs<T>();
+  constexpr int H = N / 2;
   const int g = tid / (2 * N), l = tid % (2 * N);
   const int c = l >> 1, p = l & 1;  // column (then row) index, lane parity
   const bool in_group = g < G;       // threads beyond G groups only join the barriers
@@ -264,18 +295,21 @@ __device__ __forceinline__ void gain_yz_body(const PipeArgs &a, int jx, int r, i
   }
   // column pass of one side: rows y = 2n + p of column z = c, phases, iFFT_y,
   // then column c of the buffer
-  auto col_pass = [&](int side, int m, int s, C<T>(*buf)[N + 1]) {
+  auto load_col = [&](int side, int s, C<T>(&h)[H]) {
     const C<T> *src = x_plane(a, X, slot, side, r, s, n3) + (size_t)jx * N * N;
-    const C<T> *ph = pyz + (((size_t)side * a.Nr + r) * a.M + m) * 2 * N;
-    const C<T> zph = gload(ph, N + c);
-    C<T> h[H];
 #pragma unroll
     for (int n = 0; n < H; ++n) h[n] = src[(2 * n + p) * N + c];
-#pragma unroll
-    for (int n = 0; n < H; ++n) h[n] = cmul(h[n], cmul(gload(ph, 2 * n + p), zph));
+  };
+  auto finish_col = [&](int side, int m, C<T>(&h)[H], C<T>(*buf)[N + 1]) {
+    apply_col_phase<T, N>(h, pyz + (((size_t)side * a.Nr + r) * a.M + m) * 2 * N, c, p);
     fft_pair<N, +1>(h, p);
 #pragma unroll
     for (int k = 0; k < H; ++k) buf[p * H + k][c] = h[k];
+  };
+  auto col_pass = [&](int side, int m, int s, C<T>(*buf)[N + 1]) {
+    C<T> h[H];
+    load_col(side, s, h);
+    finish_col(side, m, h, buf);
   };
   const T wscale = a.half[slot] ? (T)2 : (T)1;
   auto accumulate = [&](int m, const C<T> (&h)[H]) {
@@ -338,8 +372,35 @@ __device__ __forceinline__ void gain_yz_body(const PipeArgs &a, int jx, int r, i
         group_sync<N>();
       };
       if constexpr (US) {
-        do_side(0);
-        do_side(1);
+        // the second side's column is requested as soon as the first side's
+        // column pass has left its registers, so those loads are in flight
+        // during the first side's row pass
+        C<T> x0[H], x1[H];
+        if (active) {
+          load_col(0, s, x0);
+          finish_col(0, m, x0, lds[g]);
+          load_col(1, s, x1);
+        }
+        group_sync<N>();
+        if (active) {
+          C<T> h[H];
+#pragma unroll
+          for (int n = 0; n < H; ++n) h[n] = lds[g][c][2 * n + p];
+          fft_pair<N, +1>(h, p);
+#pragma unroll
+          for (int k = 0; k < H; ++k) u1[k] = h[k];
+        }
+        group_sync<N>();
+        if (active) finish_col(1, m, x1, lds[g]);
+        group_sync<N>();
+        if (active) {
+          C<T> h[H];
+#pragma unroll
+          for (int n = 0; n < H; ++n) h[n] = lds[g][c][2 * n + p];
+          fft_pair<N, +1>(h, p);
+          accumulate(m, h);
+        }
+        group_sync<N>();
       } else {
 #pragma unroll 1
         for (int side = 0; side < 2; ++side) do_side(side);
@@ -394,10 +455,10 @@ __device__ __forceinline__ void gain_yz_body(const PipeArgs &a, int jx, int r, i
     for (int k = 0; k < H; ++k) dst[(p * H + k) * N + c] = h[k];
   }
 }
-template <typename T, int N, int G, bool US = false>
+template <typename T, int N, int G, bool US = false, int NB = gain_bufs<T>()>
 __global__ void __launch_bounds__(G * 2 * N) k_gain_yz(PipeArgs a) {
-  __shared__ C<T> lds[G * gain_bufs<T>()][N][N + 1];
-  gain_yz_body<T, N, G, US>(a, blockIdx.x, blockIdx.y, gain_eval(a, blockIdx.z), threadIdx.x, lds);
+  __shared__ C<T> lds[G * NB][N][N + 1];
+  gain_yz_body<T, N, G, US, NB>(a, blockIdx.x, blockIdx.y, gain_eval(a, blockIdx.z), threadIdx.x, lds);
 }
 
 // ------------------------------------------------------------------ k_gain_yz2

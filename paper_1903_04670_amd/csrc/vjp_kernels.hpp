@@ -171,13 +171,10 @@ __global__ void __launch_bounds__(G * 2 * N) k_vjp_yz(VjpArgs v) {
     const int s = a.sidx[m];
     if (active) {
       const C<T> *src = x_plane(a, X, slot, uside, r, s, n3) + (size_t)jx * N * N;
-      const C<T> *ph = pyz + (((size_t)uside * a.Nr + r) * a.M + m) * 2 * N;
-      const C<T> zph = gload(ph, N + c);
       C<T> h[H];
 #pragma unroll
       for (int n = 0; n < H; ++n) h[n] = src[(2 * n + p) * N + c];
-#pragma unroll
-      for (int n = 0; n < H; ++n) h[n] = cmul(h[n], cmul(gload(ph, 2 * n + p), zph));
+      apply_col_phase<T, N>(h, pyz + (((size_t)uside * a.Nr + r) * a.M + m) * 2 * N, c, p);
       fft_pair<N, +1>(h, p);
 #pragma unroll
       for (int k = 0; k < H; ++k) buf[p * H + k][c] = h[k];
@@ -203,8 +200,17 @@ __global__ void __launch_bounds__(G * 2 * N) k_vjp_yz(VjpArgs v) {
       fft_pair<N, +1>(h, p);  // column z = c, y = pH + k
       const C<T> *ph = pyz + (((size_t)side * a.Nr + r) * a.M + m) * 2 * N;
       const C<T> zph = gload(ph, N + c);
+      if constexpr (2 * N == 64) {
+        // rows y = pH + k: ph_y(pH + k) = ph_y(k) ph_y(H)^p (wave numbers k and k - H)
+        const C<T> *phu = wave_uniform(ph);
+        const C<T> zH = cmul(zph, uload(phu, H));
+        const C<T> L{p ? zH.x : zph.x, p ? zH.y : zph.y};
 #pragma unroll
-      for (int k = 0; k < H; ++k) acc[k] = cadd(acc[k], cmul(h[k], cmul(gload(ph, p * H + k), zph)));
+        for (int k = 0; k < H; ++k) acc[k] = cadd(acc[k], cmul(h[k], cmul(uload(phu, k), L)));
+      } else {
+#pragma unroll
+        for (int k = 0; k < H; ++k) acc[k] = cadd(acc[k], cmul(h[k], cmul(gload(ph, p * H + k), zph)));
+      }
       if ((ent >> 17) & 1) {
         C<T> *dst = Y + (((size_t)side * a.Nr + r) * a.Sx + s) * n3 + (size_t)jx * N * N;
 #pragma unroll
