@@ -150,13 +150,18 @@ template <int N> __device__ __forceinline__ void group_sync() {
   }
 }
 
-// Neumaier-compensated accumulation (used by the FP32 path).
+// Compensated accumulation (used by the FP32 path): Kahan's summation with
+// the correction kept so that s + c is the running sum.  The rounding error
+// of each addition, y - (t - s), is recovered exactly and fed into the next
+// one; the error of the total is bounded by about 2 eps sum |x_i|,
+// independent of the number of terms.
 template <typename T> struct Acc {
   T s, c;
 };
 template <typename T> __device__ __forceinline__ void acc_add(T &s, T &c, T x) {
-  T t = s + x;
-  c += (fabs(s) >= fabs(x)) ? ((s - t) + x) : ((x - t) + s);
+  const T y = x + c;
+  const T t = s + y;
+  c = y - (t - s);
   s = t;
 }
 
