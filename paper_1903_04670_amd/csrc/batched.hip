@@ -90,8 +90,10 @@ __global__ void __launch_bounds__(128) kb_gain_yz(const SubItem *items, const in
     constexpr int NN = decltype(nn)::value;
     const int jx = local % NN, r = (local / NN) % si.a.Nr, e = local / (NN * si.a.Nr);
     auto *lds = reinterpret_cast<C<T>(*)[NN][NN + 1]>(smem);
+    // the phase rows follow the planes of the non-VSS body
+    auto *phs = reinterpret_cast<C<T> *>(smem + (size_t)g_gain<NN>() * gain_bufs<T>() * NN * (NN + 1) * sizeof(C<T>));
     if (si.vss) gain_yz_vss_body<T, NN, g_gain<NN>()>(si.a, jx, r, e, threadIdx.x, lds);
-    else gain_yz_body<T, NN, g_gain<NN>()>(si.a, jx, r, e, threadIdx.x, lds);
+    else gain_yz_body<T, NN, g_gain<NN>()>(si.a, jx, r, e, threadIdx.x, lds, phs);
   });
 }
 
@@ -137,7 +139,7 @@ static size_t lds_bytes(int stage, int nmax, size_t elt) {
     if (N > nmax) continue;
     const int gs = 64 / N > 0 ? 64 / N : 1, gg = 128 / (2 * N) > 0 ? 128 / (2 * N) : 1;
     const size_t plane = (size_t)N * (N + 1) * 2 * elt;
-    if (stage == kGainYZ) best = std::max(best, gg * plane * (elt == 4 ? 2 : 1));
+    if (stage == kGainYZ) best = std::max(best, gg * plane * (elt == 4 ? 2 : 1) + (size_t)gg * 4 * N * 2 * elt);
     else if (stage == kFwd || stage == kFinal) best = std::max(best, gs * plane);
   }
   return best;

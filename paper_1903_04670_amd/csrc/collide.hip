@@ -24,6 +24,16 @@ template <typename T> static int gain_variant() {
   }();
   return v;
 }
+// k_shift_x (r, s) loop split per block: $DGFS_SHIFT_SPLIT in {1, 2, 4, 8};
+// default 2 in FP64 (HBM-bound, no gain beyond) and 8 in FP32
+template <typename T> static int shift_split() {
+  static const int v = [] {
+    const char *s = std::getenv("DGFS_SHIFT_SPLIT");
+    const int x = s ? std::atoi(s) : (sizeof(T) == 8 ? 2 : 8);
+    return (x == 1 || x == 2 || x == 4 || x == 8) ? x : 2;
+  }();
+  return v;
+}
 // groups of 2N threads per k_gain_yz block: at least 128 threads per block
 template <int N> constexpr int gain_groups() { return 128 / (2 * N) > 0 ? 128 / (2 * N) : 1; }
 
@@ -38,7 +48,12 @@ static hipError_t launch_pipeline_N(const PipeArgs &a, const FwdArgs &fw, const 
   }
   const int pb = (N * N + 63) / 64;
   const int pb2 = (N * N + 31) / 32;  // lane pairs: 32 x-lines per 64-thread block
-  DGFS_LAUNCH("k_shift_x", (k_shift_x<T, N>), dim3(pb2, 2, EG), dim3(64), 0, st, a);
+  switch (shift_split<T>()) {
+    case 1: DGFS_LAUNCH("k_shift_x", (k_shift_x<T, N, 1>), dim3(pb2, 2, EG), dim3(64), 0, st, a); break;
+    case 4: DGFS_LAUNCH("k_shift_x", (k_shift_x<T, N, 4>), dim3(pb2, 8, EG), dim3(64), 0, st, a); break;
+    case 8: DGFS_LAUNCH("k_shift_x", (k_shift_x<T, N, 8>), dim3(pb2, 16, EG), dim3(64), 0, st, a); break;
+    default: DGFS_LAUNCH("k_shift_x", (k_shift_x<T, N, 2>), dim3(pb2, 4, EG), dim3(64), 0, st, a); break;
+  }
   constexpr int GG = gain_groups<N>();
   if (!vss && (gain_variant<T>() == 2 || gain_variant<T>() == 3)) {
     constexpr int G2 = gain2_pairs<N>();

@@ -227,7 +227,8 @@ __global__ void __launch_bounds__(G * N) k_fwd_yz(FwdArgs a) {
 // frequencies p*N/2 + k), then for every r and distinct sigma_x the phase
 // and the inverse transform (decimation in frequency back to x = 2n + p).
 template <typename T, int N>
-__device__ __forceinline__ void shift_x_body(const PipeArgs &a, int bx, int side, int e, int tid) {
+__device__ __forceinline__ void shift_x_body(const PipeArgs &a, int bx, int side, int e, int tid, int part = 0,
+                                             int nparts = 1) {
   constexpr int H = N / 2;
   const int pencil = bx * 32 + (tid >> 1), p = tid & 1;
   const bool valid = pencil < N * N;
@@ -244,7 +245,10 @@ __device__ __forceinline__ void shift_x_body(const PipeArgs &a, int bx, int side
   const C<T> *px = static_cast<const C<T> *>(pd.px) + (size_t)side * a.Nr * a.Sx * N;
   C<T> *X = static_cast<C<T> *>(a.X) + ((size_t)e * 2 + side) * a.Nr * a.Sx * n3;
   const bool shared = side == 1 && a.xshare[slot];
-  for (int rs = 0; rs < a.Nr * a.Sx; ++rs) {
+  // the (r, s) arrays of this block: part `part` of `nparts` equal ranges
+  const int nrs = a.Nr * a.Sx, rs_per = (nrs + nparts - 1) / nparts;
+  const int rs_end = min(nrs, (part + 1) * rs_per);
+  for (int rs = part * rs_per; rs < rs_end; ++rs) {
     if (rs >= a.Sx && a.sx_zero[rs % a.Sx]) continue;
     if (shared && a.sneg[rs % a.Sx] >= 0) continue;
     const C<T> *ph = px + (size_t)rs * N + p * H;
@@ -259,9 +263,12 @@ __device__ __forceinline__ void shift_x_body(const PipeArgs &a, int bx, int side
     }
   }
 }
-template <typename T, int N>
+// blockIdx.y = side + 2 part: the (r, s) loop is split over NP blocks per
+// (x-lines, side, eval), each redoing the cheap forward x transform, so that
+// more waves share the latency of the phase loads and stores
+template <typename T, int N, int NP = 1>
 __global__ void __launch_bounds__(64) k_shift_x(PipeArgs a) {
-  shift_x_body<T, N>(a, blockIdx.x, blockIdx.y, gain_eval(a, blockIdx.z), threadIdx.x);
+  shift_x_body<T, N>(a, blockIdx.x, blockIdx.y & 1, gain_eval(a, blockIdx.z), threadIdx.x, blockIdx.y >> 1, NP);
 }
 
 // ------------------------------------------------------------------ k_gain_yz
@@ -278,8 +285,13 @@ __global__ void __launch_bounds__(64) k_shift_x(PipeArgs a) {
 // occupancy below what its registers allow.
 template <typename T> constexpr int gain_bufs() { return sizeof(T) == 4 ? 2 : 1; }
 
+// LDS of k_gain_yz besides its planes: per group the yz phase rows of its
+// current direction, [2 sides][2N] (y phases, then z phases).
+template <typename T, int N, int G> constexpr size_t gain_phase_elems() { return (size_t)G * 4 * N; }
+
 template <typename T, int N, int G, bool US = false, int NB = gain_bufs<T>()>
-__device__ __forceinline__ void gain_yz_body(const PipeArgs &a, int jx, int r, int e, int tid, C<T> (*lds)[N][N + 1]) {
+__device__ __forceinline__ void gain_yz_body(const PipeArgs &a, int jx, int r, int e, int tid, C<T> (*lds)[N][N + 1],
+                                             C<T> *phs_all) {
   constexpr int H = N / 2;
   const int g = tid / (2 * N), l = tid % (2 * N);
   const int c = l >> 1, p = l & 1;  // column (then row) index, lane parity
@@ -305,8 +317,21 @@ __device__ __forceinline__ void gain_yz_body(const PipeArgs &a, int jx, int r, i
 #pragma unroll
     for (int n = 0; n < H; ++n) h[n] = src[(2 * n + p) * N + c];
   };
+  // The group's phase rows for its current direction are staged in LDS (one
+  // entry per lane and side, fetched one direction ahead), so the column
+  // passes read them with in-order LDS loads rather than per-lane global
+  // loads that each wait for the one before.
+  C<T> *phs = phs_all + (size_t)(in_group ? g : 0) * 4 * N;
+  C<T> pf0{0, 0}, pf1{0, 0};
+  auto fetch_ph = [&](int m) {
+    pf0 = gload(pyz + ((size_t)r * a.M + m) * 2 * N, l);
+    pf1 = gload(pyz + (((size_t)a.Nr + r) * a.M + m) * 2 * N, l);
+  };
   auto finish_col = [&](int side, int m, C<T>(&h)[H], C<T>(*buf)[N + 1]) {
-    apply_col_phase<T, N>(h, pyz + (((size_t)side * a.Nr + r) * a.M + m) * 2 * N, c, p);
+    const C<T> *ph = phs + side * 2 * N;
+    const C<T> zph = ph[N + c];
+#pragma unroll
+    for (int n = 0; n < H; ++n) h[n] = cmul(h[n], cmul(ph[2 * n + p], zph));
     fft_pair<N, +1>(h, p);
 #pragma unroll
     for (int k = 0; k < H; ++k) buf[p * H + k][c] = h[k];
@@ -334,11 +359,18 @@ __device__ __forceinline__ void gain_yz_body(const PipeArgs &a, int jx, int r, i
   const int Mx = a.half[slot] ? a.Mh : a.M;
   const int *mo = a.half[slot] ? a.mhalf : a.morder;
   const int iters = (Mx + G - 1) / G;
+  if (in_group && g < Mx) fetch_ph(mo[g]);
   for (int it = 0; it < iters; ++it) {
     const int mi = it * G + g;
     const bool active = in_group && mi < Mx;
     const int m = active ? mo[mi] : 0;
     const int s = a.sidx[m];
+    if (active) {
+      phs[l] = pf0;
+      phs[2 * N + l] = pf1;
+    }
+    group_sync<N>();
+    if (active && mi + G < Mx) fetch_ph(mo[mi + G]);
     if constexpr (NB == 2) {
       if (active) {
         col_pass(0, m, s, lds[2 * g]);
@@ -463,7 +495,8 @@ __device__ __forceinline__ void gain_yz_body(const PipeArgs &a, int jx, int r, i
 template <typename T, int N, int G, bool US = false, int NB = gain_bufs<T>()>
 __global__ void __launch_bounds__(G * 2 * N) k_gain_yz(PipeArgs a) {
   __shared__ C<T> lds[G * NB][N][N + 1];
-  gain_yz_body<T, N, G, US, NB>(a, blockIdx.x, blockIdx.y, gain_eval(a, blockIdx.z), threadIdx.x, lds);
+  __shared__ C<T> phs[gain_phase_elems<T, N, G>()];
+  gain_yz_body<T, N, G, US, NB>(a, blockIdx.x, blockIdx.y, gain_eval(a, blockIdx.z), threadIdx.x, lds, phs);
 }
 
 // ------------------------------------------------------------------ k_gain_yz2
