@@ -53,6 +53,10 @@ struct PipeArgs {
   int gslot[kMaxPairs], csrc[kMaxPairs], half[kMaxPairs];
   int Mh;
   const int *mhalf;
+  // term schedules of the gain kernel with shared column passes ([G][T],
+  // entries m | first << 16 or -1), for the full and the half set
+  const int *gs_full, *gs_half;
+  int gs_T_full, gs_T_half;
   void *Z, *X, *Cb, *V;
 };
 
@@ -359,6 +363,58 @@ __device__ __forceinline__ void gain_yz_body(const PipeArgs &a, int jx, int r, i
   const int Mx = a.half[slot] ? a.Mh : a.M;
   const int *mo = a.half[slot] ? a.mhalf : a.morder;
   const int iters = (Mx + G - 1) / G;
+  if constexpr (NB == 2 && 2 * N == 64) {
+    // Terms from the plan's schedule: directions sharing (sigma_x, sigma_y)
+    // have the same y phases, and the z phase is constant along a column, so
+    // one column pass per side (y phases only) serves every direction of the
+    // class; each term's row passes apply its own z phases.
+    const int nT = a.half[slot] ? a.gs_T_half : a.gs_T_full;
+    const int *sch = (a.half[slot] ? a.gs_half : a.gs_full) + (size_t)(in_group ? g : 0) * nT;
+    int ent_next = (in_group && nT > 0) ? sch[0] : -1;
+    if (ent_next >= 0) fetch_ph(ent_next & 0xffff);
+    for (int t = 0; t < nT; ++t) {
+      const int ent = ent_next;
+      ent_next = (in_group && t + 1 < nT) ? sch[t + 1] : -1;
+      const bool active = ent >= 0;
+      const int m = active ? (ent & 0xffff) : 0;
+      if (active) {
+        phs[l] = pf0;
+        phs[2 * N + l] = pf1;
+      }
+      group_sync<N>();
+      if (ent_next >= 0) fetch_ph(ent_next & 0xffff);
+      if (active && ((ent >> 16) & 1)) {
+        const int s = a.sidx[m];
+#pragma unroll
+        for (int side = 0; side < 2; ++side) {
+          C<T> h[H];
+          load_col(side, s, h);
+          const C<T> *ph = phs + side * 2 * N;
+#pragma unroll
+          for (int n = 0; n < H; ++n) h[n] = cmul(h[n], ph[2 * n + p]);
+          fft_pair<N, +1>(h, p);
+#pragma unroll
+          for (int k = 0; k < H; ++k) lds[2 * g + side][p * H + k][c] = h[k];
+        }
+      }
+      group_sync<N>();
+      if (active) {
+        C<T> h[H];
+        const C<T> *zp0 = phs + N;
+#pragma unroll
+        for (int n = 0; n < H; ++n) h[n] = cmul(lds[2 * g][c][2 * n + p], zp0[2 * n + p]);
+        fft_pair<N, +1>(h, p);
+#pragma unroll
+        for (int k = 0; k < H; ++k) u1[k] = h[k];
+        const C<T> *zp1 = phs + 3 * N;
+#pragma unroll
+        for (int n = 0; n < H; ++n) h[n] = cmul(lds[2 * g + 1][c][2 * n + p], zp1[2 * n + p]);
+        fft_pair<N, +1>(h, p);
+        accumulate(m, h);
+      }
+      group_sync<N>();
+    }
+  } else {
   if (in_group && g < Mx) fetch_ph(mo[g]);
   for (int it = 0; it < iters; ++it) {
     const int mi = it * G + g;
@@ -443,6 +499,7 @@ __device__ __forceinline__ void gain_yz_body(const PipeArgs &a, int jx, int r, i
         for (int side = 0; side < 2; ++side) do_side(side);
       }
     }
+  }
   }
   if constexpr (sizeof(T) == 4) {
 #pragma unroll

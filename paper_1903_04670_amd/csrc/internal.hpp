@@ -58,6 +58,10 @@ struct dgfs_plan_s {
   bool antipodal = false;
   std::vector<int> mhalf;
   const int *mhalf_dev = nullptr;      // [M/2] device copy of mhalf
+  // gain-kernel term schedules with shared column passes, full and half sets
+  int gs_T_full = 0, gs_T_half = 0;
+  std::vector<int> gs_full, gs_half;
+  const int *gs_full_dev = nullptr, *gs_half_dev = nullptr;
   // term schedule of the adjoint's yz stage: [vjp_G][vjp_T] entries
   int vjp_G = 1, vjp_T = 0;
   std::vector<int> vjp_sched;

@@ -296,19 +296,74 @@ extern "C" dgfs_status dgfs_plan_create(const dgfs_params *prm, dgfs_plan *out) 
     }
     pl->antipodal = all;
     if (all) {
-      // one representative per pair, the one seen first in sigma_x-group order
-      std::vector<int> order(M);
-      for (int m = 0; m < M; ++m) order[m] = m;
-      std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return pl->sx_idx[a] < pl->sx_idx[b]; });
+      // one representative per pair, taken in the half space sigma_x > 0 (then
+      // sigma_y > 0, then sigma_z > 0), so that representatives share
+      // (sigma_x, sigma_y) values as often as the set allows; ordered by
+      // sigma_x group, then sigma_y
+      const double tol = 1e-13;
+      auto upper = [&](int m) {
+        const double *v = &pl->sigma[3 * m];
+        if (std::fabs(v[0]) > tol) return v[0] > 0;
+        if (std::fabs(v[1]) > tol) return v[1] > 0;
+        return v[2] > 0;
+      };
       std::vector<char> taken(M, 0);
-      for (int m : order)
+      for (int m = 0; m < M; ++m)
         if (!taken[m]) {
           taken[m] = taken[anti[m]] = 1;
-          pl->mhalf.push_back(m);
+          pl->mhalf.push_back(upper(m) ? m : anti[m]);
         }
+      std::stable_sort(pl->mhalf.begin(), pl->mhalf.end(), [&](int a, int b) {
+        if (pl->sx_idx[a] != pl->sx_idx[b]) return pl->sx_idx[a] < pl->sx_idx[b];
+        return pl->sigma[3 * a + 1] < pl->sigma[3 * b + 1];
+      });
     }
   }
   const int Mh = (int)pl->mhalf.size();
+  // Gain-kernel term schedules for a block of G groups (FP32 at N = 32):
+  // directions sharing (sigma_x, sigma_y) share one column pass, so each
+  // group gets whole (sigma_x, sigma_y) classes (largest cost first onto the
+  // least loaded group); an entry is m | first << 16 (first: the column
+  // passes run before this term), padded with -1 to a common length T.
+  auto gain_sched = [&](const std::vector<int> &dirs, std::vector<int> &table) {
+    const int G = std::max(1, 128 / (2 * N));
+    std::vector<std::vector<int>> classes;
+    for (int m : dirs) {
+      int found = -1;
+      for (size_t k = 0; k < classes.size(); ++k) {
+        const int m0 = classes[k][0];
+        if (pl->sx_idx[m0] == pl->sx_idx[m] && std::fabs(pl->sigma[3 * m0 + 1] - pl->sigma[3 * m + 1]) <= 1e-15)
+          found = (int)k;
+      }
+      if (found < 0) {
+        classes.push_back({m});
+      } else {
+        classes[found].push_back(m);
+      }
+    }
+    std::stable_sort(classes.begin(), classes.end(),
+                     [](const std::vector<int> &a, const std::vector<int> &b) { return a.size() > b.size(); });
+    std::vector<std::vector<int>> lists(G);
+    std::vector<int> load(G, 0);
+    for (const auto &cl : classes) {
+      const int g = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+      for (size_t j = 0; j < cl.size(); ++j) lists[g].push_back(cl[j] | (j == 0 ? 1 << 16 : 0));
+      load[g] += 2 + 2 * (int)cl.size();
+    }
+    int T = 0;
+    for (const auto &l : lists) T = std::max<int>(T, (int)l.size());
+    table.assign((size_t)G * T, -1);
+    for (int g = 0; g < G; ++g)
+      for (size_t t = 0; t < lists[g].size(); ++t) table[(size_t)g * T + t] = lists[g][t];
+    return T;
+  };
+  {
+    std::vector<int> order(M);
+    for (int m = 0; m < M; ++m) order[m] = m;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return pl->sx_idx[a] < pl->sx_idx[b]; });
+    pl->gs_T_full = gain_sched(order, pl->gs_full);
+    pl->gs_T_half = Mh ? gain_sched(pl->mhalf, pl->gs_half) : 0;
+  }
   // VJP term schedule: the (sigma_x group, side) units of the adjoint's yz
   // stage spread over the groups of a block (largest first onto the least
   // loaded group); each group's list holds m | side << 16 | last << 17 per
@@ -342,7 +397,8 @@ extern "C" dgfs_status dgfs_plan_create(const dgfs_params *prm, dgfs_plan *out) 
       for (size_t t = 0; t < lists[g].size(); ++t) pl->vjp_sched[(size_t)g * T + t] = lists[g][t];
   }
   const int nsched = (int)pl->vjp_sched.size();
-  const size_t bytes_sidx = (((2 * M + 2 * pl->Sx + Mh + nsched) * sizeof(int) + 255) / 256) * 256;
+  const int ngf = (int)pl->gs_full.size(), ngh = (int)pl->gs_half.size();
+  const size_t bytes_sidx = (((2 * M + 2 * pl->Sx + Mh + nsched + ngf + ngh) * sizeof(int) + 255) / 256) * 256;
   pl->dev_bytes = bytes_vals + bytes_pairs + bytes_sidx;
   hipError_t he = hipMalloc(&pl->dev, pl->dev_bytes);
   if (he != hipSuccess) {
@@ -386,6 +442,11 @@ extern "C" dgfs_status dgfs_plan_create(const dgfs_params *prm, dgfs_plan *out) 
     if (Mh) std::memcpy(img.data() + bytes_vals + bytes_pairs + (2 * M + 2 * pl->Sx) * sizeof(int), pl->mhalf.data(), Mh * sizeof(int));
     std::memcpy(img.data() + bytes_vals + bytes_pairs + (2 * M + 2 * pl->Sx + Mh) * sizeof(int), pl->vjp_sched.data(),
                 nsched * sizeof(int));
+    std::memcpy(img.data() + bytes_vals + bytes_pairs + (2 * M + 2 * pl->Sx + Mh + nsched) * sizeof(int),
+                pl->gs_full.data(), ngf * sizeof(int));
+    if (ngh)
+      std::memcpy(img.data() + bytes_vals + bytes_pairs + (2 * M + 2 * pl->Sx + Mh + nsched + ngf) * sizeof(int),
+                  pl->gs_half.data(), ngh * sizeof(int));
   }
   pl->pair_dev = reinterpret_cast<PairDev *>(base + bytes_vals);
   pl->wm_dev = base + off_wm * e;
@@ -395,6 +456,8 @@ extern "C" dgfs_status dgfs_plan_create(const dgfs_params *prm, dgfs_plan *out) 
   pl->sneg_dev = pl->sidx_dev + 2 * M + pl->Sx;
   pl->mhalf_dev = Mh ? pl->sidx_dev + 2 * M + 2 * pl->Sx : nullptr;
   pl->vjp_sched_dev = pl->sidx_dev + 2 * M + 2 * pl->Sx + Mh;
+  pl->gs_full_dev = pl->vjp_sched_dev + nsched;
+  pl->gs_half_dev = ngh ? pl->gs_full_dev + ngf : nullptr;
   if (!pl->vhs) {
     dgfs_status vs = build_vss_tables(pl);
     if (vs != DGFS_OK) {
