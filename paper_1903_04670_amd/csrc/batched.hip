@@ -110,13 +110,14 @@ __global__ void __launch_bounds__(64) kb_gain_x(const SubItem *items, const int 
 }
 
 template <typename T, int NC>
-__global__ void __launch_bounds__(64) kb_final(const SubItem *items, const int *start, int n) {
+__global__ void __launch_bounds__(128) kb_final(const SubItem *items, const int *start, int n) {
   extern __shared__ __align__(16) char smem[];
   const int it = find_item(start, n, blockIdx.x), local = blockIdx.x - start[it];
   const SubItem &si = items[it];
   dispatch_N<NC>(si.N, [&](auto nn) {
     constexpr int NN = decltype(nn)::value;
-    final_yz_body<T, NN, g_small<NN>()>(si.a, si.fa, local, threadIdx.x, reinterpret_cast<C<T>(*)[NN][NN + 1]>(smem));
+    final_yz_body<T, NN, final_groups<NN>()>(si.a, si.fa, local, threadIdx.x,
+                                              reinterpret_cast<C<T>(*)[NN][NN + 1]>(smem));
   });
 }
 
@@ -129,7 +130,10 @@ static int blocks_of(int stage, const SubItem &s) {
     case kShift: return pb * 2 * E;
     case kGainYZ: return N * s.a.Nr * E;
     case kGainX: return s.vss ? pb * ((E + te - 1) / te) : pb * E;
-    default: return (N * E + gs - 1) / gs;
+    default: {
+      const int gf = 128 / (2 * N) > 0 ? 128 / (2 * N) : 1;  // final_groups<N>()
+      return (N * E + gf - 1) / gf;
+    }
   }
 }
 
@@ -140,7 +144,8 @@ static size_t lds_bytes(int stage, int nmax, size_t elt) {
     const int gs = 64 / N > 0 ? 64 / N : 1, gg = 128 / (2 * N) > 0 ? 128 / (2 * N) : 1;
     const size_t plane = (size_t)N * (N + 1) * 2 * elt;
     if (stage == kGainYZ) best = std::max(best, gg * plane * (elt == 4 ? 2 : 1) + (size_t)gg * 4 * N * 2 * elt);
-    else if (stage == kFwd || stage == kFinal) best = std::max(best, gs * plane);
+    else if (stage == kFwd) best = std::max(best, gs * plane);
+    else if (stage == kFinal) best = std::max(best, (size_t)(128 / (2 * N) > 0 ? 128 / (2 * N) : 1) * plane);
   }
   return best;
 }
@@ -219,7 +224,7 @@ static hipError_t launch_batch(const SubItem *d_items, const int *d_start, const
   if (h_total[kShift]) DGFS_LAUNCH("kb_shift", (kb_shift<T, NC>), dim3(h_total[kShift]), dim3(64), 0, st, d_items, d_start + 1 * (n + 1), n);
   if (h_total[kGainYZ]) DGFS_LAUNCH("kb_gain_yz", (kb_gain_yz<T, NC>), dim3(h_total[kGainYZ]), dim3(128), lds_bytes(kGainYZ, NC, elt), st, d_items, d_start + 2 * (n + 1), n);
   if (h_total[kGainX]) DGFS_LAUNCH("kb_gain_x", (kb_gain_x<T, NC>), dim3(h_total[kGainX]), dim3(64), 0, st, d_items, d_start + 3 * (n + 1), n);
-  if (h_total[kFinal]) DGFS_LAUNCH("kb_final", (kb_final<T, NC>), dim3(h_total[kFinal]), dim3(64), lds_bytes(kFinal, NC, elt), st, d_items, d_start + 4 * (n + 1), n);
+  if (h_total[kFinal]) DGFS_LAUNCH("kb_final", (kb_final<T, NC>), dim3(h_total[kFinal]), dim3(128), lds_bytes(kFinal, NC, elt), st, d_items, d_start + 4 * (n + 1), n);
   return hipGetLastError();
 }
 

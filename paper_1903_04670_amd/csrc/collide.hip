@@ -15,7 +15,9 @@ namespace dgfs {
 template <int N> constexpr int groups_for() { return N >= 64 ? 1 : (64 / N > 0 ? 64 / N : 1); }
 // gain kernel schedule: 1 = k_gain_yz, 2 = k_gain_yz2, 3 = k_gain_yz2 with the
 // next column prefetched, 4 = k_gain_yz with its two sides unrolled, 5 / 6 =
-// k_gain_yz (sides looped / unrolled) with one LDS plane per group
+// k_gain_yz (sides looped / unrolled) with one LDS plane per group, 7 =
+// k_gain_yz with two planes per group (the FP32 default; in FP64 it halves
+// occupancy)
 // ($DGFS_GAIN_VARIANT_FP64 / _FP32)
 template <typename T> static int gain_variant() {
   static const int v = [] {
@@ -69,6 +71,8 @@ static hipError_t launch_pipeline_N(const PipeArgs &a, const FwdArgs &fw, const 
       DGFS_LAUNCH("k_gain_yz", (k_gain_yz<T, N, GG, false, 1>), dim3(N, a.Nr, EG), dim3(GG * 2 * N), 0, st, a);
     else if (gain_variant<T>() == 6)
       DGFS_LAUNCH("k_gain_yz", (k_gain_yz<T, N, GG, true, 1>), dim3(N, a.Nr, EG), dim3(GG * 2 * N), 0, st, a);
+    else if (gain_variant<T>() == 7)
+      DGFS_LAUNCH("k_gain_yz", (k_gain_yz<T, N, GG, false, 2>), dim3(N, a.Nr, EG), dim3(GG * 2 * N), 0, st, a);
     else
       DGFS_LAUNCH("k_gain_yz", (k_gain_yz<T, N, GG>), dim3(N, a.Nr, EG), dim3(GG * 2 * N), 0, st, a);
     DGFS_LAUNCH("k_gain_x", (k_gain_x<T, N>), dim3(pb2, E), dim3(64), 0, st, a);
@@ -79,7 +83,8 @@ static hipError_t launch_pipeline_N(const PipeArgs &a, const FwdArgs &fw, const 
     DGFS_LAUNCH("k_gain_x_vss", (k_gain_x_vss<T, N, TE>), dim3(pb2, egroups), dim3(64), 0, st, a);
   }
   const int fplanes = N * a.n_nodes * fa.n_out;
-  DGFS_LAUNCH("k_final_yz", (k_final_yz<T, N, G>), dim3((fplanes + G - 1) / G), dim3(G * N), 0, st, a, fa);
+  constexpr int GF = final_groups<N>();
+  DGFS_LAUNCH("k_final_yz", (k_final_yz<T, N, GF>), dim3((fplanes + GF - 1) / GF), dim3(GF * 2 * N), 0, st, a, fa);
   return hipGetLastError();
 }
 

@@ -775,22 +775,29 @@ __global__ void __launch_bounds__(64) k_gain_x(PipeArgs a) {
 }
 
 // ------------------------------------------------------------------ k_final_yz
-// One (node, output, x-plane) per group: Q = sum over the output's pair slots
-// of beta Re(iFFT_yz V1 - f^p iFFT_yz V2).  Rows first (staged through LDS),
-// then columns so the output and f^p are accessed coalesced.
+// One (node, output, x-plane) per group of 2N threads: Q = sum over the
+// output's pair slots of beta Re(iFFT_yz V1 - f^p iFFT_yz V2).  Lane pair
+// (c, p): the row pass reads row y = c of V (z = 2n + p) and transforms it
+// along z; through LDS the column pass transforms column z = c along y and
+// ends with rows y = pH + k, so f^p and the output are accessed coalesced.
+template <int N> constexpr int final_groups() { return 128 / (2 * N) > 0 ? 128 / (2 * N) : 1; }
+
 template <typename T, int N, int G>
 __device__ __forceinline__ void final_yz_body(const PipeArgs &a, const FinalArgs &fa, int bx, int tid,
                                               C<T> (*lds)[N][N + 1]) {
-  const int g = tid / N, t = tid % N;
+  constexpr int H = N / 2;
+  const int g = tid / (2 * N), l = tid % (2 * N);
+  const int c = l >> 1, p = l & 1;
   const int plane = bx * G + g;
   const int jobs = N * a.n_nodes * fa.n_out;
   const bool active = g < G && plane < jobs;
   const int jx = plane % N, job = plane / N;
   const int node = job / fa.n_out, o = job % fa.n_out;
   const size_t n3 = (size_t)N * N * N;
-  double acc[N];
+  C<T>(*buf)[N + 1] = lds[g < G ? g : 0];
+  double acc[H];
 #pragma unroll
-  for (int y = 0; y < N; ++y) acc[y] = 0.0;
+  for (int k = 0; k < H; ++k) acc[k] = 0.0;
   const double *f = active ? fa.fsrc[o] + (size_t)node * fa.f_stride + (size_t)jx * N * N : nullptr;
   for (int j = 0; j < fa.qcount; ++j) {
     const int slot = o * fa.qcount + j;
@@ -800,46 +807,43 @@ __device__ __forceinline__ void final_yz_body(const PipeArgs &a, const FinalArgs
     for (int which = 0; which < 2; ++which) {
       if (active) {
         const C<T> *src = static_cast<const C<T> *>(a.V) + ((size_t)e * 2 + which) * n3 + (size_t)jx * N * N;
-        for (int i = t; i < N * N; i += N) lds[g][i / N][i % N] = src[i];
+        C<T> h[H];
+#pragma unroll
+        for (int n = 0; n < H; ++n) h[n] = src[c * N + 2 * n + p];
+        fft_pair<N, +1>(h, p);
+#pragma unroll
+        for (int k = 0; k < H; ++k) buf[c][p * H + k] = h[k];
       }
-      __syncthreads();
+      group_sync<N>();
       if (active) {
-        C<T> row[N];
+        C<T> h[H];
 #pragma unroll
-        for (int z = 0; z < N; ++z) row[z] = lds[g][t][z];
-        fft<N, +1>(row);
-#pragma unroll
-        for (int z = 0; z < N; ++z) lds[g][t][z] = row[z];
-      }
-      __syncthreads();
-      if (active) {
-        C<T> col[N];
-#pragma unroll
-        for (int y = 0; y < N; ++y) col[y] = lds[g][y][t];
-        fft<N, +1>(col);
+        for (int n = 0; n < H; ++n) h[n] = buf[2 * n + p][c];
+        fft_pair<N, +1>(h, p);
         // gain part, then the loss part f^p * Re(ifft(c FTg))
         if (which == 0) {
 #pragma unroll
-          for (int y = 0; y < N; ++y) acc[y] += beta * (double)col[y].x;
+          for (int k = 0; k < H; ++k) acc[k] += beta * (double)h[k].x;
         } else {
 #pragma unroll
-          for (int y = 0; y < N; ++y) acc[y] -= beta * f[y * N + t] * (double)col[y].x;
+          for (int k = 0; k < H; ++k) acc[k] -= beta * f[(p * H + k) * N + c] * (double)h[k].x;
         }
       }
-      __syncthreads();
+      group_sync<N>();
     }
   }
   if (active) {
     double *out = fa.out[o] + (size_t)node * fa.out_stride + (size_t)jx * N * N;
 #pragma unroll
-    for (int y = 0; y < N; ++y) {
-      if (fa.accumulate) out[y * N + t] += acc[y];
-      else out[y * N + t] = acc[y];
+    for (int k = 0; k < H; ++k) {
+      const int idx = (p * H + k) * N + c;
+      if (fa.accumulate) out[idx] += acc[k];
+      else out[idx] = acc[k];
     }
   }
 }
 template <typename T, int N, int G>
-__global__ void __launch_bounds__(G * N) k_final_yz(PipeArgs a, FinalArgs fa) {
+__global__ void __launch_bounds__(G * 2 * N) k_final_yz(PipeArgs a, FinalArgs fa) {
   __shared__ C<T> lds[G][N][N + 1];
   final_yz_body<T, N, G>(a, fa, blockIdx.x, threadIdx.x, lds);
 }
