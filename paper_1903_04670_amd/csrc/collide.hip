@@ -63,7 +63,7 @@ static hipError_t launch_pipeline_N(const PipeArgs &a, const FwdArgs &fw, const 
       DGFS_LAUNCH("k_gain_yz2", (k_gain_yz2<T, N, G2, true>), dim3(N, a.Nr, EG), dim3(G2 * 4 * N), 0, st, a);
     else
       DGFS_LAUNCH("k_gain_yz2", (k_gain_yz2<T, N, G2, false>), dim3(N, a.Nr, EG), dim3(G2 * 4 * N), 0, st, a);
-    DGFS_LAUNCH("k_gain_x", (k_gain_x<T, N>), dim3(pb2, E), dim3(64), 0, st, a);
+    DGFS_LAUNCH("k_gain_x", (k_gain_x<T, N, sizeof(T) == 4>), dim3(pb2, sizeof(T) == 4 ? EG : E), dim3(64), 0, st, a);
   } else if (!vss) {
     if (gain_variant<T>() == 4)
       DGFS_LAUNCH("k_gain_yz", (k_gain_yz<T, N, GG, true>), dim3(N, a.Nr, EG), dim3(GG * 2 * N), 0, st, a);
@@ -75,7 +75,7 @@ static hipError_t launch_pipeline_N(const PipeArgs &a, const FwdArgs &fw, const 
       DGFS_LAUNCH("k_gain_yz", (k_gain_yz<T, N, GG, false, 2>), dim3(N, a.Nr, EG), dim3(GG * 2 * N), 0, st, a);
     else
       DGFS_LAUNCH("k_gain_yz", (k_gain_yz<T, N, GG>), dim3(N, a.Nr, EG), dim3(GG * 2 * N), 0, st, a);
-    DGFS_LAUNCH("k_gain_x", (k_gain_x<T, N>), dim3(pb2, E), dim3(64), 0, st, a);
+    DGFS_LAUNCH("k_gain_x", (k_gain_x<T, N, sizeof(T) == 4>), dim3(pb2, sizeof(T) == 4 ? EG : E), dim3(64), 0, st, a);
   } else {
     constexpr int TE = N >= 48 ? 1 : 2;
     const int egroups = a.n_pairs * ((a.n_nodes + TE - 1) / TE);
@@ -164,6 +164,7 @@ void pipeline_slots(const dgfs_plan_s *pl, PipeArgs &a) {
   a.Mh = (int)pl->mhalf.size();
   a.mhalf = pl->mhalf_dev;
   a.n_gslots = 0;
+  for (int i = 0; i < a.n_pairs; ++i) a.cmirror[i] = -1;
   for (int i = 0; i < a.n_pairs; ++i) {
     const int p = a.pair_id[i] / pl->ns, q = a.pair_id[i] % pl->ns;
     a.csrc[i] = i;
@@ -172,8 +173,12 @@ void pipeline_slots(const dgfs_plan_s *pl, PipeArgs &a) {
     if (share && p != q && pl->mirror_ok(p, q))
       for (int j = 0; j < i; ++j)
         if (a.csrc[j] == j && a.pair_id[j] == q * pl->ns + p && a.zp[j] == a.zq[i] && a.zq[j] == a.zp[i]) src = j;
-    if (src >= 0) a.csrc[i] = src;
-    else a.gslot[a.n_gslots++] = i;
+    if (src >= 0) {
+      a.csrc[i] = src;
+      a.cmirror[src] = i;
+    } else {
+      a.gslot[a.n_gslots++] = i;
+    }
   }
 }
 

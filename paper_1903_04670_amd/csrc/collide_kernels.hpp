@@ -51,6 +51,7 @@ struct PipeArgs {
   // mhalf (one direction of each antipodal pair) with doubled weights.
   int n_gslots;
   int gslot[kMaxPairs], csrc[kMaxPairs], half[kMaxPairs];
+  int cmirror[kMaxPairs];  // the slot that reads this slot's C_r arrays, or -1
   int Mh;
   const int *mhalf;
   // term schedules of the gain kernel with shared column passes ([G][T],
@@ -698,80 +699,97 @@ __global__ void __launch_bounds__(G2 * 4 * N) k_gain_yz2(PipeArgs a) {
 }
 
 // ------------------------------------------------------------------ k_gain_x
-// Lane pair = x-line (y, z) of one eval: QG = sum_r g_r(|k|) FFT_x C_r, then
-// V1 = iFFT_x QG and V2 = iFFT_x(c(|k|) FFT_x Z_q).
-template <typename T, int N>
+// Lane pair = x-line (y, z) of one gain slot: QG = sum_r g_r(|k|) FFT_x C_r,
+// then V1 = iFFT_x QG and V2 = iFFT_x(c(|k|) FFT_x Z_q).  A slot whose C_r
+// are reused by a mirrored slot (q, p) serves it in the same pass when FUSE
+// is set: each FFT_x C_r is multiplied by both pairs' gain tables (the FP32
+// kernel; in FP64 the second accumulator costs more occupancy than it saves).
+template <typename T, int N, bool FUSE = false>
 __device__ __forceinline__ void gain_x_body(const PipeArgs &a, int bx, int e, int tid) {
   constexpr int H = N / 2;
   const int pencil = bx * 32 + (tid >> 1), p = tid & 1;
   const bool valid = pencil < N * N;
   const int pc = valid ? pencil : 0;
   const int node = e / a.n_pairs, slot = e % a.n_pairs;
+  const int slot2 = FUSE ? a.cmirror[slot] : -1;
+  const bool two = slot2 >= 0;
   const PairDev pd = a.pairs[a.pair_id[slot]];
+  const PairDev pd2 = a.pairs[a.pair_id[two ? slot2 : slot]];
   const size_t n3 = (size_t)N * N * N;
   const int K2 = 3 * (N / 2) * (N / 2) + 1;
   const int vy = wave_idx(pc / N, N), vz = wave_idx(pc % N, N);
   const int kyz = vy * vy + vz * vz;
-  const T *gt = static_cast<const T *>(pd.gtab);
+  const T *gt = static_cast<const T *>(pd.gtab), *gt2 = static_cast<const T *>(pd2.gtab);
   const C<T> *Cb = static_cast<const C<T> *>(a.Cb) + (size_t)(node * a.n_pairs + a.csrc[slot]) * a.Nr * n3;
-  C<T> Q[H];
+  C<T> Q[H], Q2[H];
   T Qcx[sizeof(T) == 4 ? H : 1], Qcy[sizeof(T) == 4 ? H : 1];
+  T Qcx2[sizeof(T) == 4 ? H : 1], Qcy2[sizeof(T) == 4 ? H : 1];
 #pragma unroll
-  for (int k = 0; k < H; ++k) Q[k] = C<T>{0, 0};
+  for (int k = 0; k < H; ++k) Q[k] = Q2[k] = C<T>{0, 0};
   if constexpr (sizeof(T) == 4) {
 #pragma unroll
-    for (int k = 0; k < H; ++k) Qcx[k] = Qcy[k] = 0;
+    for (int k = 0; k < H; ++k) Qcx[k] = Qcy[k] = Qcx2[k] = Qcy2[k] = 0;
   }
+  auto acc = [&](C<T>(&q)[H], T(&cx)[sizeof(T) == 4 ? H : 1], T(&cy)[sizeof(T) == 4 ? H : 1], const T *g,
+                 const C<T>(&w)[H]) {
+#pragma unroll
+    for (int k = 0; k < H; ++k) {
+      const int vx = wave_idx(p * H + k, N);
+      const T gv = gload(g, vx * vx);
+      if constexpr (sizeof(T) == 4) {
+        acc_add(q[k].x, cx[k], gv * w[k].x);
+        acc_add(q[k].y, cy[k], gv * w[k].y);
+      } else {
+        q[k].x += gv * w[k].x;
+        q[k].y += gv * w[k].y;
+      }
+    }
+  };
   for (int r = 0; r < a.Nr; ++r) {
     C<T> w[H];
     const C<T> *src = Cb + (size_t)r * n3;
 #pragma unroll
     for (int n = 0; n < H; ++n) w[n] = src[(size_t)(2 * n + p) * N * N + pc];
     fft_pair<N, -1>(w, p);
-    const T *g = gt + (size_t)r * K2 + kyz;
+    acc(Q, Qcx, Qcy, gt + (size_t)r * K2 + kyz, w);
+    if (two) acc(Q2, Qcx2, Qcy2, gt2 + (size_t)r * K2 + kyz, w);
+  }
+  // V1 = iFFT_x QG, and the loss part V2 = iFFT_x(c(|k|) FFT_x Z_q), per served slot
+  auto finish = [&](C<T>(&q)[H], T(&cx)[sizeof(T) == 4 ? H : 1], T(&cy)[sizeof(T) == 4 ? H : 1], int sl,
+                    const PairDev &pdv) {
+    if constexpr (sizeof(T) == 4) {
+#pragma unroll
+      for (int k = 0; k < H; ++k) q[k] = C<T>{q[k].x + cx[k], q[k].y + cy[k]};
+    }
+    fft_pair_dif<N, +1>(q, p);
+    C<T> *V = static_cast<C<T> *>(a.V) + (size_t)(node * a.n_pairs + sl) * 2 * n3;
+    if (valid) {
+#pragma unroll
+      for (int k = 0; k < H; ++k) V[(size_t)(2 * k + p) * N * N + pc] = q[k];
+    }
+    const C<T> *Zq = static_cast<const C<T> *>(a.Z) + ((size_t)node * a.nz + a.zq[sl]) * n3;
+#pragma unroll
+    for (int n = 0; n < H; ++n) q[n] = Zq[(size_t)(2 * n + p) * N * N + pc];
+    fft_pair<N, -1>(q, p);
+    const T *ct = static_cast<const T *>(pdv.ctab) + kyz;
 #pragma unroll
     for (int k = 0; k < H; ++k) {
       const int vx = wave_idx(p * H + k, N);
-      const T gv = gload(g, vx * vx);
-      if constexpr (sizeof(T) == 4) {
-        acc_add(Q[k].x, Qcx[k], gv * w[k].x);
-        acc_add(Q[k].y, Qcy[k], gv * w[k].y);
-      } else {
-        Q[k].x += gv * w[k].x;
-        Q[k].y += gv * w[k].y;
-      }
+      q[k] = cscale(q[k], gload(ct, vx * vx));
     }
-  }
-  if constexpr (sizeof(T) == 4) {
+    fft_pair_dif<N, +1>(q, p);
+    if (valid) {
 #pragma unroll
-    for (int k = 0; k < H; ++k) Q[k] = C<T>{Q[k].x + Qcx[k], Q[k].y + Qcy[k]};
-  }
-  fft_pair_dif<N, +1>(Q, p);
-  C<T> *V = static_cast<C<T> *>(a.V) + (size_t)e * 2 * n3;
-  if (valid) {
-#pragma unroll
-    for (int k = 0; k < H; ++k) V[(size_t)(2 * k + p) * N * N + pc] = Q[k];
-  }
-  // loss: c(|k|) * FFT_x Z_q, back along x
-  const C<T> *Zq = static_cast<const C<T> *>(a.Z) + ((size_t)node * a.nz + a.zq[slot]) * n3;
-#pragma unroll
-  for (int n = 0; n < H; ++n) Q[n] = Zq[(size_t)(2 * n + p) * N * N + pc];
-  fft_pair<N, -1>(Q, p);
-  const T *ct = static_cast<const T *>(pd.ctab) + kyz;
-#pragma unroll
-  for (int k = 0; k < H; ++k) {
-    const int vx = wave_idx(p * H + k, N);
-    Q[k] = cscale(Q[k], gload(ct, vx * vx));
-  }
-  fft_pair_dif<N, +1>(Q, p);
-  if (valid) {
-#pragma unroll
-    for (int k = 0; k < H; ++k) V[n3 + (size_t)(2 * k + p) * N * N + pc] = Q[k];
-  }
+      for (int k = 0; k < H; ++k) V[n3 + (size_t)(2 * k + p) * N * N + pc] = q[k];
+    }
+  };
+  finish(Q, Qcx, Qcy, slot, pd);
+  if (two) finish(Q2, Qcx2, Qcy2, slot2, pd2);
 }
-template <typename T, int N>
+// FUSE: one block per gain slot (blockIdx.y over gain slots); else one per slot
+template <typename T, int N, bool FUSE>
 __global__ void __launch_bounds__(64) k_gain_x(PipeArgs a) {
-  gain_x_body<T, N>(a, blockIdx.x, blockIdx.y, threadIdx.x);
+  gain_x_body<T, N, FUSE>(a, blockIdx.x, FUSE ? gain_eval(a, blockIdx.y) : (int)blockIdx.y, threadIdx.x);
 }
 
 // ------------------------------------------------------------------ k_final_yz
