@@ -115,7 +115,10 @@ def measured_traffic(kernel):
             vals[k.strip()] = float(v)
     if vals.get("sha") != h.hexdigest():
         return None
-    return vals.get(kernel)
+    for k, v in vals.items():
+        if k == kernel or k.startswith(kernel):
+            return v
+    return None
 
 
 def gain_schedule(cfg):
@@ -376,7 +379,7 @@ def main():
         roof = {"bound": "alu", "achieved": round(achieved_tf, 2), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(alu_frac, 4)}
     roof.update({"traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
-                 "traffic": measured_traffic("%s<double, %d, 2>" % (name, cfg["N"])), "kernel": name,
+                 "traffic": measured_traffic("%s<double, %d," % (name, cfg["N"])), "kernel": name,
                  "avg_launch_ms": round(avg_ms, 4),
                  "evals_per_launch": evals_per_launch, "gain_slots_per_node": gpp + gpq,
                  "direction_terms_per_node": gterms, "algorithmic_bytes_per_launch": bytes_launch,
