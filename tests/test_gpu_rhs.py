@@ -95,6 +95,27 @@ def test_symmetric_gain_schedule_three_species(torch_cuda, sphere, monkeypatch):
     assert rel_linf(got, full) <= 1e-13
 
 
+def test_couette_full_size_rhs_sampled_nodes(torch_cuda):
+    """The benchmark's workload at full size (64 nodes, two species, N = 32,
+    M = 12, N_rho = 16) in the launch configuration the benchmark times: the
+    collision part of dgfs_rhs over all nodes (several launches, mirrored and
+    half-set gain slots) against the oracle at the first and the last node,
+    and each sampled node bit-identical to a call on that node alone."""
+    from paper_1903_04670_amd import dgfs
+    torch = torch_cuda
+    cfg = wl.couette_two_species()
+    pl = gpu_plan(cfg)
+    F = torch.from_numpy(cfg["F"]).cuda()
+    got = dgfs.rhs(pl, F).cpu().numpy()
+    opl = oracle_pairs(cfg)
+    for i in (0, cfg["n_nodes"] - 1):
+        ref = mixture_collision(opl, cfg["F"][i:i + 1])[0]
+        assert rel_linf(got[i], ref) <= TOL, i
+        alone = dgfs.rhs(pl, F[i:i + 1].contiguous()).cpu().numpy()[0]
+        assert np.array_equal(alone, got[i]), i
+    assert np.isfinite(got).all()
+
+
 def test_projected_rhs_conserves(torch_cuda):
     """With DGFS_PROJECT the collision term of each node has zero mass per
     species and zero total momentum and energy (to rounding), and equals the

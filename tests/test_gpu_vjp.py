@@ -38,14 +38,16 @@ def test_vjp_matches_oracle_gradient(torch_cuda, N, kind):
             assert rel_linf(gq[i].cpu().numpy(), rq) <= 1e-11, (p, q, i)
 
 
-def test_vjp_central_differences_N32(torch_cuda):
-    """Two species (masses 1, 2.5), N = 32, icosahedron, N_rho = 16, 4 nodes:
-    <wbar, dQ> by central differences (eps = 1e-6, relative to |f|_inf)
-    along 16 random directions equals <grad, d>.  Q is bilinear, so the
-    difference quotient is exact up to rounding."""
+@pytest.mark.parametrize("n_nodes,n_dirs", [(4, 16), (256, 64)])
+def test_vjp_central_differences_N32(torch_cuda, n_nodes, n_dirs):
+    """Two species (masses 1, 2.5), N = 32, icosahedron, N_rho = 16, on 4
+    nodes and on the differentiation workload's full 256 nodes: <wbar, dQ>
+    by central differences (eps = 1e-6, relative to |f|_inf) along random
+    directions equals <grad, d>.  Q is bilinear, so the difference quotient
+    is exact up to rounding."""
     from paper_1903_04670_amd import dgfs
     torch = torch_cuda
-    cfg = wl.differentiation(n_nodes=4)
+    cfg = wl.differentiation(n_nodes=n_nodes)
     pl = gpu_plan(cfg)
     F = torch.from_numpy(cfg["F"]).cuda()
     W = torch.from_numpy(cfg["W"][:, 0]).cuda()
@@ -53,7 +55,7 @@ def test_vjp_central_differences_N32(torch_cuda):
     p, q = 0, 1
     gf, gq = dgfs.collide_vjp(pl, p, q, F[:, p].contiguous(), F[:, q].contiguous(), W)
     worst = 0.0
-    for k in range(16):
+    for k in range(n_dirs):
         d = torch.randn(F[:, p].shape, generator=gen, dtype=torch.float64).cuda()
         d = d * (F.abs().max() / d.abs().max())
         eps = 1e-6
