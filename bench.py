@@ -318,7 +318,7 @@ def bench_vss(args):
     from paper_1903_04670_amd import dgfs, workloads as wl
     cfg = wl.precision_vss(n_nodes=4)
     F = torch.from_numpy(cfg["F"]).cuda()
-    res = {}
+    res, kern = {}, {}
     for prec in ("fp64", "fp32"):
         plan = dgfs.Plan(cfg["masses"], cfg["omega"], cfg["alpha"], cfg["N"], cfg["L"], cfg["Nrho"],
                          sphere=cfg["sphere"], M=cfg["M"], R=cfg["R"], precision=prec)
@@ -327,10 +327,16 @@ def bench_vss(args):
         t = _time_cuda(lambda: dgfs.rhs(plan, F, out=out, project=(prec == "fp32"), ws=ws),
                        max(1, args.steps // 2), 1)
         res[prec] = 36 / t
+        dgfs.profile_enable(True)
+        dgfs.rhs(plan, F, out=out, project=(prec == "fp32"), ws=ws)
+        torch.cuda.synchronize()
+        kern[prec] = {k: round(v[1], 3) for k, v in sorted(dgfs.profile_read().items())}
+        dgfs.profile_enable(False)
         del plan, ws
         torch.cuda.empty_cache()
     return {"metric": "collision evals/s, 3-species VSS N=48^3 M=32 N_rho=24", "value": round(res["fp64"], 1),
-            "unit": "collision evals/s", "fp32_mixed": round(res["fp32"], 1), "n_gpus": 1, "dtype": "f64",
+            "unit": "collision evals/s", "fp32_mixed": round(res["fp32"], 1),
+            "kernels_ms_per_pass": kern, "n_gpus": 1, "dtype": "f64",
             "data": "synthetic", "config": {"workload": cfg["name"], "nodes": 4, "pairs": 9}}
 
 

@@ -13,19 +13,6 @@
 namespace dgfs {
 
 template <int N> constexpr int groups_for() { return N >= 64 ? 1 : (64 / N > 0 ? 64 / N : 1); }
-// gain kernel schedule: 1 = k_gain_yz, 2 = k_gain_yz2, 3 = k_gain_yz2 with the
-// next column prefetched, 4 = k_gain_yz with its two sides unrolled, 5 / 6 =
-// k_gain_yz (sides looped / unrolled) with one LDS plane per group, 7 =
-// k_gain_yz with two planes per group (the FP32 default; in FP64 it halves
-// occupancy)
-// ($DGFS_GAIN_VARIANT_FP64 / _FP32)
-template <typename T> static int gain_variant() {
-  static const int v = [] {
-    const char *s = std::getenv(sizeof(T) == 8 ? "DGFS_GAIN_VARIANT_FP64" : "DGFS_GAIN_VARIANT_FP32");
-    return s ? std::atoi(s) : 1;
-  }();
-  return v;
-}
 // k_shift_x (r, s) loop split per block: $DGFS_SHIFT_SPLIT in {1, 2, 4, 8};
 // default 2 in FP64 (HBM-bound, no gain beyond) and 8 in FP32
 template <typename T> static int shift_split() {
@@ -48,7 +35,6 @@ static hipError_t launch_pipeline_N(const PipeArgs &a, const FwdArgs &fw, const 
     const int planes = N * fw.n_nodes * fw.nz;
     DGFS_LAUNCH("k_fwd_yz", (k_fwd_yz<T, N, G>), dim3((planes + G - 1) / G), dim3(G * N), 0, st, fw);
   }
-  const int pb = (N * N + 63) / 64;
   const int pb2 = (N * N + 31) / 32;  // lane pairs: 32 x-lines per 64-thread block
   switch (shift_split<T>()) {
     case 1: DGFS_LAUNCH("k_shift_x", (k_shift_x<T, N, 1>), dim3(pb2, 2, EG), dim3(64), 0, st, a); break;
@@ -57,24 +43,8 @@ static hipError_t launch_pipeline_N(const PipeArgs &a, const FwdArgs &fw, const 
     default: DGFS_LAUNCH("k_shift_x", (k_shift_x<T, N, 2>), dim3(pb2, 4, EG), dim3(64), 0, st, a); break;
   }
   constexpr int GG = gain_groups<N>();
-  if (!vss && (gain_variant<T>() == 2 || gain_variant<T>() == 3)) {
-    constexpr int G2 = gain2_pairs<N>();
-    if (gain_variant<T>() == 3)
-      DGFS_LAUNCH("k_gain_yz2", (k_gain_yz2<T, N, G2, true>), dim3(N, a.Nr, EG), dim3(G2 * 4 * N), 0, st, a);
-    else
-      DGFS_LAUNCH("k_gain_yz2", (k_gain_yz2<T, N, G2, false>), dim3(N, a.Nr, EG), dim3(G2 * 4 * N), 0, st, a);
-    DGFS_LAUNCH("k_gain_x", (k_gain_x<T, N, sizeof(T) == 4>), dim3(pb2, sizeof(T) == 4 ? EG : E), dim3(64), 0, st, a);
-  } else if (!vss) {
-    if (gain_variant<T>() == 4)
-      DGFS_LAUNCH("k_gain_yz", (k_gain_yz<T, N, GG, true>), dim3(N, a.Nr, EG), dim3(GG * 2 * N), 0, st, a);
-    else if (gain_variant<T>() == 5)
-      DGFS_LAUNCH("k_gain_yz", (k_gain_yz<T, N, GG, false, 1>), dim3(N, a.Nr, EG), dim3(GG * 2 * N), 0, st, a);
-    else if (gain_variant<T>() == 6)
-      DGFS_LAUNCH("k_gain_yz", (k_gain_yz<T, N, GG, true, 1>), dim3(N, a.Nr, EG), dim3(GG * 2 * N), 0, st, a);
-    else if (gain_variant<T>() == 7)
-      DGFS_LAUNCH("k_gain_yz", (k_gain_yz<T, N, GG, false, 2>), dim3(N, a.Nr, EG), dim3(GG * 2 * N), 0, st, a);
-    else
-      DGFS_LAUNCH("k_gain_yz", (k_gain_yz<T, N, GG>), dim3(N, a.Nr, EG), dim3(GG * 2 * N), 0, st, a);
+  if (!vss) {
+    DGFS_LAUNCH("k_gain_yz", (k_gain_yz<T, N, GG>), dim3(N, a.Nr, EG), dim3(GG * 2 * N), 0, st, a);
     DGFS_LAUNCH("k_gain_x", (k_gain_x<T, N, sizeof(T) == 4>), dim3(pb2, sizeof(T) == 4 ? EG : E), dim3(64), 0, st, a);
   } else {
     constexpr int TE = N >= 48 ? 1 : 2;

@@ -294,7 +294,7 @@ template <typename T> constexpr int gain_bufs() { return sizeof(T) == 4 ? 2 : 1;
 // current direction, [2 sides][2N] (y phases, then z phases).
 template <typename T, int N, int G> constexpr size_t gain_phase_elems() { return (size_t)G * 4 * N; }
 
-template <typename T, int N, int G, bool US = false, int NB = gain_bufs<T>()>
+template <typename T, int N, int G, int NB = gain_bufs<T>()>
 __device__ __forceinline__ void gain_yz_body(const PipeArgs &a, int jx, int r, int e, int tid, C<T> (*lds)[N][N + 1],
                                              C<T> *phs_all) {
   constexpr int H = N / 2;
@@ -465,40 +465,8 @@ __device__ __forceinline__ void gain_yz_body(const PipeArgs &a, int jx, int r, i
         }
         group_sync<N>();
       };
-      if constexpr (US) {
-        // the second side's column is requested as soon as the first side's
-        // column pass has left its registers, so those loads are in flight
-        // during the first side's row pass
-        C<T> x0[H], x1[H];
-        if (active) {
-          load_col(0, s, x0);
-          finish_col(0, m, x0, lds[g]);
-          load_col(1, s, x1);
-        }
-        group_sync<N>();
-        if (active) {
-          C<T> h[H];
-#pragma unroll
-          for (int n = 0; n < H; ++n) h[n] = lds[g][c][2 * n + p];
-          fft_pair<N, +1>(h, p);
-#pragma unroll
-          for (int k = 0; k < H; ++k) u1[k] = h[k];
-        }
-        group_sync<N>();
-        if (active) finish_col(1, m, x1, lds[g]);
-        group_sync<N>();
-        if (active) {
-          C<T> h[H];
-#pragma unroll
-          for (int n = 0; n < H; ++n) h[n] = lds[g][c][2 * n + p];
-          fft_pair<N, +1>(h, p);
-          accumulate(m, h);
-        }
-        group_sync<N>();
-      } else {
 #pragma unroll 1
-        for (int side = 0; side < 2; ++side) do_side(side);
-      }
+      for (int side = 0; side < 2; ++side) do_side(side);
     }
   }
   }
@@ -550,152 +518,11 @@ __device__ __forceinline__ void gain_yz_body(const PipeArgs &a, int jx, int r, i
     for (int k = 0; k < H; ++k) dst[(p * H + k) * N + c] = h[k];
   }
 }
-template <typename T, int N, int G, bool US = false, int NB = gain_bufs<T>()>
+template <typename T, int N, int G, int NB = gain_bufs<T>()>
 __global__ void __launch_bounds__(G * 2 * N) k_gain_yz(PipeArgs a) {
   __shared__ C<T> lds[G * NB][N][N + 1];
   __shared__ C<T> phs[gain_phase_elems<T, N, G>()];
-  gain_yz_body<T, N, G, US, NB>(a, blockIdx.x, blockIdx.y, gain_eval(a, blockIdx.z), threadIdx.x, lds, phs);
-}
-
-// ------------------------------------------------------------------ k_gain_yz2
-// Alternative schedule of the same computation: a block holds G2 pairs of
-// groups (2N threads each); in a pair, group 0 computes u1 and group 1 u2 of
-// the same direction, so each wave does half the passes of a term and only
-// group 1 keeps the accumulator.  The registers freed that way hold the next
-// direction's X column, loaded while the current one is transformed.
-// u1 reaches group 1 through group 0's LDS buffer in a private layout: lane
-// (c, p) stores z = p*N/2 + k at slot 2k + p, the slots it read itself.
-template <typename T, int N, int G2, bool PF>
-__device__ __forceinline__ void gain_yz2_body(const PipeArgs &a, int jx, int r, int e, int tid, C<T> (*lds)[N][N + 1]) {
-  constexpr int H = N / 2;
-  const int grp = tid / (2 * N), l = tid % (2 * N);
-  const int c = l >> 1, p = l & 1;
-  const int g2 = grp >> 1, side = grp & 1;
-  const bool in_pair = g2 < G2;
-  const int slot = e % a.n_pairs;
-  const PairDev pd = a.pairs[a.pair_id[slot]];
-  const size_t n3 = (size_t)N * N * N;
-  const C<T> *X = static_cast<const C<T> *>(a.X) + (size_t)e * 2 * a.Nr * a.Sx * n3;
-  const T *wm = static_cast<const T *>(a.wm);
-  const C<T> *pyz = static_cast<const C<T> *>(pd.pyz);
-  C<T>(*own)[N + 1] = lds[in_pair ? 2 * g2 + side : 0];
-  C<T>(*ubuf)[N + 1] = lds[in_pair ? 2 * g2 : 0];
-  C<T> P[H], raw[H];
-  T Pcx[sizeof(T) == 4 ? H : 1], Pcy[sizeof(T) == 4 ? H : 1];
-#pragma unroll
-  for (int k = 0; k < H; ++k) P[k] = C<T>{0, 0};
-  if constexpr (sizeof(T) == 4) {
-#pragma unroll
-    for (int k = 0; k < H; ++k) Pcx[k] = Pcy[k] = 0;
-  }
-  const int Mx = a.half[slot] ? a.Mh : a.M;
-  const int *mo = a.half[slot] ? a.mhalf : a.morder;
-  const T wscale = a.half[slot] ? (T)2 : (T)1;
-  auto load_col = [&](int mi) {
-    const int m = mo[mi];
-    const C<T> *src = x_plane(a, X, slot, side, r, a.sidx[m], n3) + (size_t)jx * N * N;
-#pragma unroll
-    for (int n = 0; n < H; ++n) raw[n] = src[(2 * n + p) * N + c];
-  };
-  if (PF && in_pair && g2 < Mx) load_col(g2);
-  const int iters = (Mx + G2 - 1) / G2;
-  for (int it = 0; it < iters; ++it) {
-    const int mi = it * G2 + g2;
-    const bool active = in_pair && mi < Mx;
-    const int m = active ? mo[mi] : 0;
-    if (active) {
-      if (!PF) load_col(mi);
-      const C<T> *ph = pyz + (((size_t)side * a.Nr + r) * a.M + m) * 2 * N;
-      const C<T> zph = gload(ph, N + c);
-      C<T> h[H];
-#pragma unroll
-      for (int n = 0; n < H; ++n) h[n] = cmul(raw[n], cmul(gload(ph, 2 * n + p), zph));
-      if (PF && mi + G2 < Mx) load_col(mi + G2);  // next direction's column, in flight during this term
-      fft_pair<N, +1>(h, p);
-#pragma unroll
-      for (int k = 0; k < H; ++k) own[p * H + k][c] = h[k];
-    }
-    __syncthreads();
-    C<T> h[H];
-    if (active) {
-#pragma unroll
-      for (int n = 0; n < H; ++n) h[n] = own[c][2 * n + p];
-      fft_pair<N, +1>(h, p);
-      if (side == 0) {
-#pragma unroll
-        for (int k = 0; k < H; ++k) own[c][2 * k + p] = h[k];
-      }
-    }
-    __syncthreads();
-    if (active && side == 1) {
-      const T w = uload(wm, m) * wscale;
-#pragma unroll
-      for (int k = 0; k < H; ++k) {
-        const C<T> pr = cmul(ubuf[c][2 * k + p], h[k]);
-        if constexpr (sizeof(T) == 4) {
-          acc_add(P[k].x, Pcx[k], w * pr.x);
-          acc_add(P[k].y, Pcy[k], w * pr.y);
-        } else {
-          P[k].x += w * pr.x;
-          P[k].y += w * pr.y;
-        }
-      }
-    }
-    __syncthreads();
-  }
-  const bool holder = in_pair && side == 1;
-  if constexpr (sizeof(T) == 4) {
-#pragma unroll
-    for (int k = 0; k < H; ++k) P[k] = C<T>{P[k].x + Pcx[k], P[k].y + Pcy[k]};
-  }
-  if (holder) {
-#pragma unroll
-    for (int k = 0; k < H; ++k) lds[2 * g2][c][p * H + k] = P[k];
-  }
-  __syncthreads();
-  const bool lead = holder && g2 == 0;
-  if (lead) {
-    C<T> h[H];
-#pragma unroll
-    for (int n = 0; n < H; ++n) {
-      T sx = lds[0][c][2 * n + p].x, sy = lds[0][c][2 * n + p].y, cx = 0, cy = 0;
-      for (int q = 1; q < G2; ++q) {
-        const C<T> v = lds[2 * q][c][2 * n + p];
-        if constexpr (sizeof(T) == 4) {
-          acc_add(sx, cx, v.x);
-          acc_add(sy, cy, v.y);
-        } else {
-          sx += v.x;
-          sy += v.y;
-        }
-      }
-      h[n] = C<T>{sx + cx, sy + cy};
-    }
-    fft_pair<N, -1>(h, p);
-#pragma unroll
-    for (int k = 0; k < H; ++k) P[k] = h[k];
-  }
-  __syncthreads();
-  if (lead) {
-#pragma unroll
-    for (int k = 0; k < H; ++k) lds[0][c][p * H + k] = P[k];
-  }
-  __syncthreads();
-  if (lead) {
-    C<T> h[H];
-#pragma unroll
-    for (int n = 0; n < H; ++n) h[n] = lds[0][2 * n + p][c];
-    fft_pair<N, -1>(h, p);
-    C<T> *dst = static_cast<C<T> *>(a.Cb) + ((size_t)e * a.Nr + r) * n3 + (size_t)jx * N * N;
-#pragma unroll
-    for (int k = 0; k < H; ++k) dst[(p * H + k) * N + c] = h[k];
-  }
-}
-template <int N> constexpr int gain2_pairs() { return 128 / (4 * N) > 0 ? 128 / (4 * N) : 1; }
-template <typename T, int N, int G2, bool PF>
-__global__ void __launch_bounds__(G2 * 4 * N) k_gain_yz2(PipeArgs a) {
-  __shared__ C<T> lds[2 * G2][N][N + 1];
-  gain_yz2_body<T, N, G2, PF>(a, blockIdx.x, blockIdx.y, gain_eval(a, blockIdx.z), threadIdx.x, lds);
+  gain_yz_body<T, N, G, NB>(a, blockIdx.x, blockIdx.y, gain_eval(a, blockIdx.z), threadIdx.x, lds, phs);
 }
 
 // ------------------------------------------------------------------ k_gain_x
