@@ -16,7 +16,7 @@ namespace dgfs {
 
 template <typename T, int N, int G>
 __device__ __forceinline__ void gain_yz_vss_body(const PipeArgs &a, int jx, int r, int e, int tid,
-                                                 C<T> (*lds)[N][N + 1]) {
+                                                 C<T> (*lds)[N][N + 1], C<T> *phs_all) {
   constexpr int H = N / 2;
   const int g = tid / (2 * N), l = tid % (2 * N);
   const int c = l >> 1, p = l & 1;
@@ -27,23 +27,39 @@ __device__ __forceinline__ void gain_yz_vss_body(const PipeArgs &a, int jx, int 
   const C<T> *pyz = static_cast<const C<T> *>(pd.pyz);
   C<T> *Cout = static_cast<C<T> *>(a.Cb) + ((size_t)e * a.Nr + r) * a.M * n3 + (size_t)jx * N * N;
   C<T> u1[H];
+  // phase rows of the group's current direction staged in LDS, fetched one
+  // direction ahead (as in the VHS gain kernel)
+  const bool in_group = g < G;
+  C<T> *phs = phs_all + (size_t)(in_group ? g : 0) * 4 * N;
+  C<T> pf0{0, 0}, pf1{0, 0};
+  auto fetch_ph = [&](int m) {
+    pf0 = gload(pyz + ((size_t)r * a.M + m) * 2 * N, l);
+    pf1 = gload(pyz + (((size_t)a.Nr + r) * a.M + m) * 2 * N, l);
+  };
+  if (in_group && g < a.M) fetch_ph(a.morder[g]);
   const int iters = (a.M + G - 1) / G;
   for (int it = 0; it < iters; ++it) {
     const int mi = it * G + g;
-    const bool active = g < G && mi < a.M;
+    const bool active = in_group && mi < a.M;
     const int m = active ? a.morder[mi] : 0;
     const int s = a.sidx[m];
+    if (active) {
+      phs[l] = pf0;
+      phs[2 * N + l] = pf1;
+    }
+    group_sync<N>();
+    if (active && mi + G < a.M) fetch_ph(a.morder[mi + G]);
 #pragma unroll 1
     for (int side = 0; side < 2; ++side) {
       if (active) {
         const C<T> *src = x_plane(a, X, slot, side, r, s, n3) + (size_t)jx * N * N;
-        const C<T> *ph = pyz + (((size_t)side * a.Nr + r) * a.M + m) * 2 * N;
-        const C<T> zph = gload(ph, N + c);
+        const C<T> *ph = phs + side * 2 * N;
+        const C<T> zph = ph[N + c];
         C<T> h[H];
 #pragma unroll
         for (int n = 0; n < H; ++n) h[n] = src[(2 * n + p) * N + c];
 #pragma unroll
-        for (int n = 0; n < H; ++n) h[n] = cmul(h[n], cmul(gload(ph, 2 * n + p), zph));
+        for (int n = 0; n < H; ++n) h[n] = cmul(h[n], cmul(ph[2 * n + p], zph));
         fft_pair<N, +1>(h, p);
 #pragma unroll
         for (int k = 0; k < H; ++k) lds[g][p * H + k][c] = h[k];
@@ -86,7 +102,8 @@ __device__ __forceinline__ void gain_yz_vss_body(const PipeArgs &a, int jx, int 
 template <typename T, int N, int G>
 __global__ void __launch_bounds__(G * 2 * N) k_gain_yz_vss(PipeArgs a) {
   __shared__ C<T> lds[G][N][N + 1];
-  gain_yz_vss_body<T, N, G>(a, blockIdx.x, blockIdx.y, gain_eval(a, blockIdx.z), threadIdx.x, lds);
+  __shared__ C<T> phs[G * 4 * N];
+  gain_yz_vss_body<T, N, G>(a, blockIdx.x, blockIdx.y, gain_eval(a, blockIdx.z), threadIdx.x, lds, phs);
 }
 
 template <typename T, int N, int TE>
