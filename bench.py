@@ -361,7 +361,7 @@ def main():
     r64, r32 = res["fp64"], res["fp32"]
     value = evals_per_step / (r64["ms"] / 1e3)
     # dominant kernel roofline (FP64 path)
-    name = "k_gain_yz2" if "k_gain_yz2" in r64["kern"] else "k_gain_yz"
+    name = "k_gain_yz"
     cnt, tot = r64["kern"].get(name, (0, 0.0))
     if cnt == 0:
         raise RuntimeError("no gain-kernel launches were recorded")
