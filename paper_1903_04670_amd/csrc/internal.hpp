@@ -63,9 +63,9 @@ struct dgfs_plan_s {
   std::vector<int> gs_full, gs_half;
   const int *gs_full_dev = nullptr, *gs_half_dev = nullptr;
   // term schedule of the adjoint's yz stage: [vjp_G][vjp_T] entries
-  int vjp_G = 1, vjp_T = 0;
-  std::vector<int> vjp_sched;
-  const int *vjp_sched_dev = nullptr;
+  int vjp_G = 1, vjp_T = 0, vjp_T_sym = 0;
+  std::vector<int> vjp_sched, vjp_sched_sym;  // all units; side-0 units only
+  const int *vjp_sched_dev = nullptr, *vjp_sched_sym_dev = nullptr;
   // the m-sum of the gain product of (q, p) equals that of (p, q)
   bool mirror_ok(int p, int q) const {
     return vhs && antipodal && pairs[p * ns + q].R == pairs[q * ns + p].R;

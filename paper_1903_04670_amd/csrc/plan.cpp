@@ -364,39 +364,45 @@ extern "C" dgfs_status dgfs_plan_create(const dgfs_params *prm, dgfs_plan *out) 
     pl->gs_T_full = gain_sched(order, pl->gs_full);
     pl->gs_T_half = Mh ? gain_sched(pl->mhalf, pl->gs_half) : 0;
   }
-  // VJP term schedule: the (sigma_x group, side) units of the adjoint's yz
+  // VJP term schedules: the (sigma_x group, side) units of the adjoint's yz
   // stage spread over the groups of a block (largest first onto the least
   // loaded group); each group's list holds m | side << 16 | last << 17 per
   // term (last: the unit ends, write its sum), padded with -1 to a common
-  // length so every group passes the same barriers.
+  // length so every group passes the same barriers.  The second schedule
+  // holds the side-0 units only: with p == q on one input and an antipodal
+  // sphere set the two sides' gain sums coincide (see dgfs_collide_vjp).
   {
     const int G = std::max(1, 128 / (2 * N));
     std::vector<int> cnt(pl->Sx, 0);
     for (int m = 0; m < M; ++m) ++cnt[pl->sx_idx[m]];
-    std::vector<std::pair<int, int>> units;  // (s, side)
-    for (int s = 0; s < pl->Sx; ++s)
-      for (int side = 0; side < 2; ++side) units.push_back({s, side});
-    std::stable_sort(units.begin(), units.end(), [&](const std::pair<int, int> &a, const std::pair<int, int> &b) {
-      return cnt[a.first] > cnt[b.first];
-    });
-    std::vector<std::vector<int>> lists(G);
-    std::vector<int> load(G, 0);
-    for (const auto &u : units) {
-      const int g = (int)(std::min_element(load.begin(), load.end()) - load.begin());
-      int left = cnt[u.first];
-      for (int m = 0; m < M; ++m)
-        if (pl->sx_idx[m] == u.first) lists[g].push_back(m | (u.second << 16) | ((--left == 0) ? 1 << 17 : 0));
-      load[g] += cnt[u.first];
-    }
-    int T = 0;
-    for (const auto &l : lists) T = std::max<int>(T, (int)l.size());
+    auto build = [&](int nsides, std::vector<int> &table) {
+      std::vector<std::pair<int, int>> units;  // (s, side)
+      for (int s = 0; s < pl->Sx; ++s)
+        for (int side = 0; side < nsides; ++side) units.push_back({s, side});
+      std::stable_sort(units.begin(), units.end(), [&](const std::pair<int, int> &a, const std::pair<int, int> &b) {
+        return cnt[a.first] > cnt[b.first];
+      });
+      std::vector<std::vector<int>> lists(G);
+      std::vector<int> load(G, 0);
+      for (const auto &u : units) {
+        const int g = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        int left = cnt[u.first];
+        for (int m = 0; m < M; ++m)
+          if (pl->sx_idx[m] == u.first) lists[g].push_back(m | (u.second << 16) | ((--left == 0) ? 1 << 17 : 0));
+        load[g] += cnt[u.first];
+      }
+      int T = 0;
+      for (const auto &l : lists) T = std::max<int>(T, (int)l.size());
+      table.assign((size_t)G * T, -1);
+      for (int g = 0; g < G; ++g)
+        for (size_t t = 0; t < lists[g].size(); ++t) table[(size_t)g * T + t] = lists[g][t];
+      return T;
+    };
     pl->vjp_G = G;
-    pl->vjp_T = T;
-    pl->vjp_sched.assign((size_t)G * T, -1);
-    for (int g = 0; g < G; ++g)
-      for (size_t t = 0; t < lists[g].size(); ++t) pl->vjp_sched[(size_t)g * T + t] = lists[g][t];
+    pl->vjp_T = build(2, pl->vjp_sched);
+    pl->vjp_T_sym = build(1, pl->vjp_sched_sym);
   }
-  const int nsched = (int)pl->vjp_sched.size();
+  const int nsched = (int)pl->vjp_sched.size() + (int)pl->vjp_sched_sym.size();
   const int ngf = (int)pl->gs_full.size(), ngh = (int)pl->gs_half.size();
   const size_t bytes_sidx = (((2 * M + 2 * pl->Sx + Mh + nsched + ngf + ngh) * sizeof(int) + 255) / 256) * 256;
   pl->dev_bytes = bytes_vals + bytes_pairs + bytes_sidx;
@@ -441,7 +447,9 @@ extern "C" dgfs_status dgfs_plan_create(const dgfs_params *prm, dgfs_plan *out) 
     std::memcpy(img.data() + bytes_vals + bytes_pairs + (2 * M + pl->Sx) * sizeof(int), neg.data(), pl->Sx * sizeof(int));
     if (Mh) std::memcpy(img.data() + bytes_vals + bytes_pairs + (2 * M + 2 * pl->Sx) * sizeof(int), pl->mhalf.data(), Mh * sizeof(int));
     std::memcpy(img.data() + bytes_vals + bytes_pairs + (2 * M + 2 * pl->Sx + Mh) * sizeof(int), pl->vjp_sched.data(),
-                nsched * sizeof(int));
+                pl->vjp_sched.size() * sizeof(int));
+    std::memcpy(img.data() + bytes_vals + bytes_pairs + (2 * M + 2 * pl->Sx + Mh + pl->vjp_sched.size()) * sizeof(int),
+                pl->vjp_sched_sym.data(), pl->vjp_sched_sym.size() * sizeof(int));
     std::memcpy(img.data() + bytes_vals + bytes_pairs + (2 * M + 2 * pl->Sx + Mh + nsched) * sizeof(int),
                 pl->gs_full.data(), ngf * sizeof(int));
     if (ngh)
@@ -456,6 +464,7 @@ extern "C" dgfs_status dgfs_plan_create(const dgfs_params *prm, dgfs_plan *out) 
   pl->sneg_dev = pl->sidx_dev + 2 * M + pl->Sx;
   pl->mhalf_dev = Mh ? pl->sidx_dev + 2 * M + 2 * pl->Sx : nullptr;
   pl->vjp_sched_dev = pl->sidx_dev + 2 * M + 2 * pl->Sx + Mh;
+  pl->vjp_sched_sym_dev = pl->vjp_sched_dev + pl->vjp_sched.size();
   pl->gs_full_dev = pl->vjp_sched_dev + nsched;
   pl->gs_half_dev = ngh ? pl->gs_full_dev + ngf : nullptr;
   if (!pl->vhs) {

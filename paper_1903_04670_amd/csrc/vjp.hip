@@ -48,7 +48,10 @@ static hipError_t launch_vjp_N(const VjpArgs &v, const FwdArgs &fw, hipStream_t 
   DGFS_LAUNCH("k_vjp_v", (k_vjp_v<T, N>), dim3(pb2, E), dim3(64), 0, st, v);
   constexpr int GV = 128 / (2 * N) > 0 ? 128 / (2 * N) : 1;  // groups per block, as the plan's VJP schedule
   DGFS_LAUNCH("k_vjp_yz", (k_vjp_yz<T, N, GV>), dim3(N, a.Nr, E), dim3(GV * 2 * N), 0, st, v);
-  DGFS_LAUNCH("k_vjp_x", (k_vjp_x<T, N>), dim3(pb2, E), dim3(64), 0, st, v);
+  if (v.sym)
+    DGFS_LAUNCH("k_vjp_x", (k_vjp_x<T, N, true>), dim3(pb2, E), dim3(64), 0, st, v);
+  else
+    DGFS_LAUNCH("k_vjp_x", (k_vjp_x<T, N, false>), dim3(pb2, E), dim3(64), 0, st, v);
   const int planes_o = N * a.n_nodes;
   DGFS_LAUNCH("k_vjp_final", (k_vjp_final<T, N, G>), dim3((planes_o + G - 1) / G), dim3(G * N), 0, st, v);
   return hipGetLastError();
@@ -109,14 +112,20 @@ extern "C" dgfs_status dgfs_collide_vjp(dgfs_plan pl, int64_t n_nodes, int32_t p
   v.a.pair_id[0] = p * pl->ns + q;
   v.a.zp[0] = 0;
   v.a.zq[0] = 1;
-  v.a.xshare[0] = 0;
+  // p == q on one input: the second side's x-shifted arrays are the first
+  // side's of the opposite sigma_x; with an antipodal sphere set the two
+  // sides' gain sums coincide as well (the gain part of Q(f, g) is then
+  // symmetric in f and g), so only side 0's sums are formed
+  const bool same = p == q && fp == fq;
+  v.a.xshare[0] = same ? 1 : 0;
   pipeline_slots(pl, v.a);
+  v.sym = (same && pl->antipodal) ? 1 : 0;
   v.f_stride = node_stride;
   v.w_stride = wbar_stride;
   v.g_stride = grad_stride;
   v.accumulate = (flags & DGFS_ACCUMULATE) ? 1 : 0;
-  v.sched = pl->vjp_sched_dev;
-  v.sched_T = pl->vjp_T;
+  v.sched = v.sym ? pl->vjp_sched_sym_dev : pl->vjp_sched_dev;
+  v.sched_T = v.sym ? pl->vjp_T_sym : pl->vjp_T;
   for (int64_t n0 = 0; n0 < n_nodes; n0 += B) {
     const int nb = (int)std::min<int64_t>(B, n_nodes - n0);
     v.a.n_nodes = nb;

@@ -34,6 +34,7 @@ struct VjpArgs {
   int accumulate;
   const int *sched;     // [G][sched_T] term schedule of k_vjp_yz (m | side << 16 | last << 17, or -1)
   int sched_T;
+  int sym;              // 1: the two sides' gain sums coincide; only side 0's Y is formed
 };
 
 // iFFT_yz of wbar and of f*wbar on plane jx of each node (rows first through
@@ -228,8 +229,8 @@ __global__ void __launch_bounds__(G * 2 * N) k_vjp_yz(VjpArgs v) {
 // inverse x transforms of the decimated halves give wave numbers pH + k, the
 // phases and tables act there, and a decimation-in-frequency transform
 // returns to x = 2k + p.
-template <typename T, int N>
-__global__ void __launch_bounds__(64) k_vjp_x(VjpArgs v) {
+template <typename T, int N, bool SYM>
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) k_vjp_x(VjpArgs v) {
   constexpr int H = N / 2;
   const PipeArgs &a = v.a;
   const int pencil = blockIdx.x * 32 + (threadIdx.x >> 1), p = threadIdx.x & 1;
@@ -243,9 +244,9 @@ __global__ void __launch_bounds__(64) k_vjp_x(VjpArgs v) {
   const C<T> *Y = static_cast<const C<T> *>(v.Y) + (size_t)e * 2 * a.Nr * a.Sx * n3;
   C<T> *Hs = static_cast<C<T> *>(v.H) + (size_t)e * 3 * n3;
   const T *ct = static_cast<const T *>(pd.ctab) + kyz;
-  for (int side = 0; side < 2; ++side) {
+  // G = sum_rs P_x,rs iFFT_x Y_side,rs of one side
+  auto gain_sum = [&](int side, C<T>(&G)[H]) {
     const C<T> *px = static_cast<const C<T> *>(pd.px) + (size_t)side * a.Nr * a.Sx * N;
-    C<T> G[H];
 #pragma unroll
     for (int k = 0; k < H; ++k) G[k] = C<T>{0, 0};
     for (int rs = 0; rs < a.Nr * a.Sx; ++rs) {
@@ -258,27 +259,42 @@ __global__ void __launch_bounds__(64) k_vjp_x(VjpArgs v) {
 #pragma unroll
       for (int k = 0; k < H; ++k) G[k] = cadd(G[k], cmul(w[k], gload(ph, k)));
     }
-    if (side == 1) {  // minus c(|k|) iFFT_x(Zfw) / N^3
-      const C<T> *Zfw = static_cast<const C<T> *>(v.Zw) + ((size_t)node * 2 + 1) * n3;
-      C<T> w[H];
+  };
+  // out = G - c(|k|) iFFT_x(Zfw) / N^3 (the g-side loss), in place of w
+  auto minus_loss = [&](const C<T>(&G)[H], C<T>(&w)[H]) {
+    const C<T> *Zfw = static_cast<const C<T> *>(v.Zw) + ((size_t)node * 2 + 1) * n3;
 #pragma unroll
-      for (int n = 0; n < H; ++n) w[n] = Zfw[(size_t)(2 * n + p) * N * N + pc];
-      fft_pair<N, +1>(w, p);
+    for (int n = 0; n < H; ++n) w[n] = Zfw[(size_t)(2 * n + p) * N * N + pc];
+    fft_pair<N, +1>(w, p);
 #pragma unroll
-      for (int k = 0; k < H; ++k) {
-        const int vx = wave_idx(p * H + k, N);
-        G[k] = csub(G[k], cscale(w[k], gload(ct, vx * vx)));
-      }
+    for (int k = 0; k < H; ++k) {
+      const int vx = wave_idx(p * H + k, N);
+      w[k] = csub(G[k], cscale(w[k], gload(ct, vx * vx)));
     }
+  };
+  auto store_h = [&](int which, C<T>(&G)[H]) {
     fft_pair_dif<N, -1>(G, p);
     if (valid) {
 #pragma unroll
-      for (int k = 0; k < H; ++k) Hs[(size_t)side * n3 + (size_t)(2 * k + p) * N * N + pc] = G[k];
+      for (int k = 0; k < H; ++k) Hs[(size_t)which * n3 + (size_t)(2 * k + p) * N * N + pc] = G[k];
     }
+  };
+  C<T> G[H], w[H];
+  gain_sum(0, G);
+  if constexpr (SYM) {
+    // p == q on one input with an antipodal sphere set: side 1's gain sum is
+    // side 0's (only side 0's Y was formed)
+    minus_loss(G, w);
+    store_h(1, w);
+    store_h(0, G);
+  } else {
+    store_h(0, G);
+    gain_sum(1, G);
+    minus_loss(G, w);
+    store_h(1, w);
   }
   // Vf = iFFT_x(c FFT_x Z_g) / N^3
   const C<T> *Zg = static_cast<const C<T> *>(a.Z) + ((size_t)node * a.nz + a.zq[slot]) * n3;
-  C<T> w[H];
 #pragma unroll
   for (int n = 0; n < H; ++n) w[n] = Zg[(size_t)(2 * n + p) * N * N + pc];
   fft_pair<N, -1>(w, p);

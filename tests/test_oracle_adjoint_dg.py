@@ -144,3 +144,33 @@ def test_ssp_rk3_third_order():
         errs.append(abs(y - math.exp(lam)))
     rates = [math.log2(a / b) for a, b in zip(errs, errs[1:])]
     assert min(rates) > 2.9, rates
+
+
+@pytest.mark.parametrize("sphere,symmetric", [("icosahedron", True), ("octahedron", True), ("fibonacci", False)])
+def test_gain_part_is_symmetric_for_antipodal_sets(sphere, symmetric):
+    """For p == q and a sphere set closed under sigma -> -sigma (equal
+    weights) the gain part of Q(f, g) is a symmetric bilinear form, so at
+    f == g its derivatives along any direction d with respect to f and to g
+    agree (the adjoint then needs one side's gain sums only).  Checked by
+    central differences of the oracle's gain part, which is exact for a
+    bilinear map up to rounding; a Fibonacci set is not antipodal and the
+    two differ."""
+    from oracle.collide import PairPlan, collide_gain_loss
+    from oracle.quadrature import sphere_set
+    N, L = 6, 4.0
+    s, w = sphere_set(sphere, 7 if sphere == "fibonacci" else None)
+    pl = PairPlan(N, L, 1.0, 1.0, 0.6, 1.0, 3, s, w, R=5.0)
+    rng = np.random.default_rng(5)
+    f = rng.random((N, N, N))
+    wb = rng.standard_normal((N, N, N))
+    d = rng.standard_normal((N, N, N))
+
+    def gain(a, b):
+        return collide_gain_loss(pl, a, b)[0]
+    e = 1e-3
+    df = float(((gain(f + e * d, f) - gain(f - e * d, f)) * wb).sum() / (2 * e))
+    dg = float(((gain(f, f + e * d) - gain(f, f - e * d)) * wb).sum() / (2 * e))
+    if symmetric:
+        assert abs(df - dg) <= 1e-10 * abs(df)
+    else:
+        assert abs(df - dg) > 1e-3 * abs(df)
