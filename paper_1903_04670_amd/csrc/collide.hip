@@ -84,26 +84,33 @@ hipError_t launch_pipeline(const dgfs_plan_s *pl, const PipeArgs &a, const FwdAr
 
 static size_t align256(size_t b) { return (b + 255) / 256 * 256; }
 
-// Evaluations per launch when no tuned width is known ($DGFS_CHUNK_EVALS).
-// 128 measured best at N = 32 (64 gives the same FP64 rate and 7% less in
-// FP32; 8-32 leave the GPU underfilled).
+// Evaluations per launch when no tuned width is known ($DGFS_CHUNK_EVALS,
+// 0 = the default for the plan's precision).
 int max_evals_per_chunk() {
   static int v = [] {
     const char *s = std::getenv("DGFS_CHUNK_EVALS");
-    int x = s ? std::atoi(s) : 128;
-    return x > 0 ? x : 128;
+    const int x = s ? std::atoi(s) : 0;
+    return x > 0 ? x : 0;
   }();
   return v;
 }
 
+// Nodes per launch.  The width in evaluations comes from the autotuner's
+// cache, $DGFS_CHUNK_EVALS, or the default (measured at N = 32: 128 in FP64,
+// 256 in FP32; 8-32 leave the GPU underfilled); a chunk's intermediates stay
+// within 16 GiB (the VSS path stores every (r, m) term; HBM holds 288 GB);
+// and the nodes are split evenly over the launches this needs, so no launch
+// is a short tail.
 int chunk_nodes(const dgfs_plan_s *pl, int64_t n_nodes, int n_pairs) {
-  const int evals = pl->chunk_evals > 0 ? pl->chunk_evals : max_evals_per_chunk();
+  int evals = pl->chunk_evals > 0 ? pl->chunk_evals : max_evals_per_chunk();
+  if (evals <= 0) evals = pl->precision == DGFS_FP64 ? 128 : 256;
   int64_t b = std::max<int64_t>(1, evals / n_pairs);
-  // keep a chunk's intermediates within 8 GiB (the VSS path stores every (r, m) term)
   const size_t per_node = pipeline_bytes(pl, 1, n_pairs, std::min(pl->ns, 2 * n_pairs));
-  const int64_t cap = std::max<int64_t>(1, (int64_t)((size_t)8 << 30) / (int64_t)per_node);
-  b = std::min(b, cap);
-  return (int)std::max<int64_t>(1, std::min<int64_t>(b, n_nodes));
+  const int64_t cap = std::max<int64_t>(1, (int64_t)((size_t)16 << 30) / (int64_t)per_node);
+  b = std::max<int64_t>(1, std::min(b, cap));
+  if (n_nodes <= b) return (int)std::max<int64_t>(1, n_nodes);
+  const int64_t launches = (n_nodes + b - 1) / b;
+  return (int)((n_nodes + launches - 1) / launches);
 }
 
 size_t pipeline_bytes(const dgfs_plan_s *pl, int B, int n_pairs, int nz) {
