@@ -98,3 +98,36 @@ def test_vss_N48_fp32_mixed_vs_fp64_and_projection(torch_cuda):
         res = np.max(np.abs(mom)) / np.max(np.abs(scale))
         print("node %d conservation residual after projection: %.3e" % (i, res))
         assert res < 1e-12
+
+
+def test_vss_full_size_512_nodes_properties(torch_cuda):
+    """The precision workload at full size (512 nodes, three species, N = 48,
+    M = 32 Fibonacci, N_rho = 24, alpha = 1.4): at every node the FP32-mixed
+    collision term with the FP64 projection is within the stated bound of
+    the projected FP64 term, and conserves mass of each species, momentum
+    and energy to round-off (checked on the GPU in FP64)."""
+    from paper_1903_04670_amd import dgfs, workloads as wl
+    torch = torch_cuda
+    cfg = wl.precision_vss(n_nodes=512)
+    n, ns, N = cfg["n_nodes"], cfg["ns"], cfg["N"]
+    F = torch.from_numpy(cfg["F"]).cuda()
+    del cfg["F"]
+    p64 = gpu_plan(cfg, precision="fp64")
+    ref = dgfs.rhs(p64, F)
+    del p64
+    p32 = gpu_plan(cfg, precision="fp32")
+    got = dgfs.rhs(p32, F, project=True)
+    del p32, F
+    C = torch.from_numpy(cons.constraint_rows(N, cfg["L"], cfg["masses"]).reshape(ns + 4, -1)).cuda()
+    G = C @ C.T
+    refm = ref.reshape(n, -1).T                      # [ns N^3, nodes]
+    lam = torch.linalg.solve(G, C @ refm)
+    ref_proj = (refm - C.T @ lam).T.reshape(got.shape)
+    err = float((got - ref_proj).abs().max() / ref_proj.abs().max())
+    print("512 nodes, N=48 VSS fp32-mixed+projection vs fp64+projection: rel Linf %.3e" % err)
+    assert err < 1e-3
+    mom = C @ got.reshape(n, -1).T                   # [ns + 4, nodes]
+    scale = C @ ref.abs().reshape(n, -1).T
+    res = float((mom.abs() / scale.abs().max(dim=0).values).max())
+    print("worst conservation residual after projection over 512 nodes: %.3e" % res)
+    assert res < 1e-12
