@@ -346,18 +346,25 @@ __device__ __forceinline__ void gain_yz_body(const PipeArgs &a, int jx, int r, i
     load_col(side, s, h);
     finish_col(side, m, h, buf);
   };
+  // The quadrature weight w_m (doubled on a half set) rides on side 0's z
+  // phase row when it is staged: that row is constant along each column and
+  // enters u1 linearly, so the product below needs no separate scaling.
   const T wscale = a.half[slot] ? (T)2 : (T)1;
-  auto accumulate = [&](int m, const C<T> (&h)[H]) {
-    const T w = uload(wm, m) * wscale;
+  auto stage_ph = [&](int m) {
+    const T ws = l >= N ? uload(wm, m) * wscale : (T)1;
+    phs[l] = C<T>{pf0.x * ws, pf0.y * ws};
+    phs[2 * N + l] = pf1;
+  };
+  auto accumulate = [&](const C<T> (&h)[H]) {
 #pragma unroll
     for (int k = 0; k < H; ++k) {
       const C<T> pr = cmul(u1[k], h[k]);
       if constexpr (sizeof(T) == 4) {
-        acc_add(P[k].x, Pcx[k], w * pr.x);
-        acc_add(P[k].y, Pcy[k], w * pr.y);
+        acc_add(P[k].x, Pcx[k], pr.x);
+        acc_add(P[k].y, Pcy[k], pr.y);
       } else {
-        P[k].x += w * pr.x;
-        P[k].y += w * pr.y;
+        P[k].x += pr.x;
+        P[k].y += pr.y;
       }
     }
   };
@@ -378,10 +385,7 @@ __device__ __forceinline__ void gain_yz_body(const PipeArgs &a, int jx, int r, i
       ent_next = (in_group && t + 1 < nT) ? sch[t + 1] : -1;
       const bool active = ent >= 0;
       const int m = active ? (ent & 0xffff) : 0;
-      if (active) {
-        phs[l] = pf0;
-        phs[2 * N + l] = pf1;
-      }
+      if (active) stage_ph(m);
       group_sync<N>();
       if (ent_next >= 0) fetch_ph(ent_next & 0xffff);
       if (active && ((ent >> 16) & 1)) {
@@ -411,7 +415,7 @@ __device__ __forceinline__ void gain_yz_body(const PipeArgs &a, int jx, int r, i
 #pragma unroll
         for (int n = 0; n < H; ++n) h[n] = cmul(lds[2 * g + 1][c][2 * n + p], zp1[2 * n + p]);
         fft_pair<N, +1>(h, p);
-        accumulate(m, h);
+        accumulate(h);
       }
       group_sync<N>();
     }
@@ -422,10 +426,7 @@ __device__ __forceinline__ void gain_yz_body(const PipeArgs &a, int jx, int r, i
     const bool active = in_group && mi < Mx;
     const int m = active ? mo[mi] : 0;
     const int s = a.sidx[m];
-    if (active) {
-      phs[l] = pf0;
-      phs[2 * N + l] = pf1;
-    }
+    if (active) stage_ph(m);
     group_sync<N>();
     if (active && mi + G < Mx) fetch_ph(mo[mi + G]);
     if constexpr (NB == 2) {
@@ -444,7 +445,7 @@ __device__ __forceinline__ void gain_yz_body(const PipeArgs &a, int jx, int r, i
 #pragma unroll
         for (int n = 0; n < H; ++n) h[n] = lds[2 * g + 1][c][2 * n + p];
         fft_pair<N, +1>(h, p);
-        accumulate(m, h);
+        accumulate(h);
       }
       group_sync<N>();
     } else {
@@ -460,7 +461,7 @@ __device__ __forceinline__ void gain_yz_body(const PipeArgs &a, int jx, int r, i
 #pragma unroll
             for (int k = 0; k < H; ++k) u1[k] = h[k];
           } else {
-            accumulate(m, h);
+            accumulate(h);
           }
         }
         group_sync<N>();
