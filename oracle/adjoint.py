@@ -10,12 +10,14 @@ the gradient of <wbar, Re(A x)> is Re(A^T wbar).  Transposing each factor:
   dQ/dg^T wbar = beta Re F( sum_rm P2 * iF(u1 * F(W * iF wbar)) )
                  - beta Re F(c * iF(f * wbar))
 u1, u2 are recomputed per (r, m).  When p = q and one array feeds both
-arguments, its gradient is the sum of the two.
+arguments, its gradient is the sum of the two.  With plan.nyquist_zero the
+gain's translates are formed from Z F f and Z F g, Z the (diagonal,
+symmetric) Nyquist-plane mask, so Z joins P1 and P2.
 """
 import numpy as np
 
 from . import dft
-from .collide import phase_argument
+from .collide import nyquist_mask, phase_argument
 
 
 def collide_vjp(plan, f, g, wbar):
@@ -24,11 +26,12 @@ def collide_vjp(plan, f, g, wbar):
     u = dft.ifft3(wbar)
     acc_f = np.zeros_like(FTf)
     acc_g = np.zeros_like(FTg)
+    z = nyquist_mask(plan.N) if plan.nyquist_zero else 1.0
     for r in range(len(plan.rho)):
         for m in range(len(plan.sigma)):
             a = phase_argument(plan, r, m)
-            P1 = np.exp(1j * mq / (mp + mq) * a)
-            P2 = np.exp(-1j * mp / (mp + mq) * a)
+            P1 = np.exp(1j * mq / (mp + mq) * a) * z
+            P2 = np.exp(-1j * mp / (mp + mq) * a) * z
             u1 = dft.ifft3(P1 * FTf)
             u2 = dft.ifft3(P2 * FTg)
             v = dft.fft3(plan.w_rho[r] * plan.w_sigma[m] * plan.b[r, m] * u)

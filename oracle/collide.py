@@ -27,11 +27,18 @@ class PairPlan:
     sigma, w_sigma  sphere quadrature (M points, weights summing to 4 pi)
     beta        prefactor; None => unit reduced Knudsen number (beta_reduced)
     gamma, eta  override the kernel exponents (Krook-Wu uses gamma = eta = 0)
+    nyquist_zero  form the gain's translates t1, t2 from fft(f^p), fft(f^q)
+                with their Nyquist planes (wave index -N/2 on any axis) set
+                to zero; the loss term is unchanged.  Then t1 and t2 are
+                Hermitian, so u1 = ifft(t1) and u2 = ifft(t2) are real.
+                This variant is not in the paper (whose Algorithm 2 keeps the
+                Nyquist planes and takes Re() at the end).
     """
 
     def __init__(self, N, L, mp, mq, omega, alpha, Nrho, sigma, w_sigma,
-                 R=None, beta=None, gamma=None, eta=None):
+                 R=None, beta=None, gamma=None, eta=None, nyquist_zero=False):
         self.N, self.L, self.mp, self.mq = N, L, float(mp), float(mq)
+        self.nyquist_zero = bool(nyquist_zero)
         g, e = kernel_exponents(omega, alpha)
         self.gamma = g if gamma is None else gamma
         self.eta = e if eta is None else eta
@@ -51,20 +58,39 @@ def phase_argument(plan, r, m):
     return math.pi / plan.L * plan.rho[r] * (lx * s[0] + ly * s[1] + lz * s[2])
 
 
+def nyquist_mask(N):
+    """1 on the N^3 wave grid except where some axis has wave index -N/2
+    (storage index N/2), which is 0."""
+    keep = np.ones(N)
+    keep[N // 2] = 0.0
+    return keep[:, None, None] * keep[None, :, None] * keep[None, None, :]
+
+
+def gain_spectra(plan, FTf, FTg):
+    """The transforms the gain's translates are formed from: FTf, FTg as
+    they are, or with their Nyquist planes zeroed (plan.nyquist_zero)."""
+    if not plan.nyquist_zero:
+        return FTf, FTg
+    z = nyquist_mask(plan.N)
+    return z * FTf, z * FTg
+
+
 def collide(plan, f, g):
     """Q = beta Re(ifft(QG) - f * ifft(c * FTg)), Algorithm 2.
 
     f = F^p and g = F^q are real N^3 arrays.  The (r, m) loop runs r outer,
-    m inner, in increasing order."""
+    m inner, in increasing order.  With plan.nyquist_zero, t1 and t2 are
+    formed from the Nyquist-zeroed transforms (gain_spectra)."""
     mp, mq = plan.mp, plan.mq
     FTf = dft.fft3(f)
     FTg = dft.fft3(g)
+    Gf, Gg = gain_spectra(plan, FTf, FTg)
     QG = np.zeros_like(FTf)
     for r in range(len(plan.rho)):
         for m in range(len(plan.sigma)):
             a = phase_argument(plan, r, m)
-            t1 = np.exp(1j * mq / (mp + mq) * a) * FTf
-            t2 = np.exp(-1j * mp / (mp + mq) * a) * FTg
+            t1 = np.exp(1j * mq / (mp + mq) * a) * Gf
+            t2 = np.exp(-1j * mp / (mp + mq) * a) * Gg
             t3 = dft.fft3(dft.ifft3(t1) * dft.ifft3(t2))
             QG = QG + plan.w_rho[r] * plan.w_sigma[m] * plan.b[r, m] * t3
     return plan.beta * np.real(dft.ifft3(QG) - f * dft.ifft3(plan.c * FTg))
@@ -75,12 +101,13 @@ def collide_gain_loss(plan, f, g):
     (beta Re ifft(QG), beta Re(f * ifft(c FTg)))."""
     mp, mq = plan.mp, plan.mq
     FTf, FTg = dft.fft3(f), dft.fft3(g)
+    Gf, Gg = gain_spectra(plan, FTf, FTg)
     QG = np.zeros_like(FTf)
     for r in range(len(plan.rho)):
         for m in range(len(plan.sigma)):
             a = phase_argument(plan, r, m)
-            t1 = np.exp(1j * mq / (mp + mq) * a) * FTf
-            t2 = np.exp(-1j * mp / (mp + mq) * a) * FTg
+            t1 = np.exp(1j * mq / (mp + mq) * a) * Gf
+            t2 = np.exp(-1j * mp / (mp + mq) * a) * Gg
             QG = QG + plan.w_rho[r] * plan.w_sigma[m] * plan.b[r, m] * \
                 dft.fft3(dft.ifft3(t1) * dft.ifft3(t2))
     gain = plan.beta * np.real(dft.ifft3(QG))
@@ -112,6 +139,8 @@ def collide_direct(plan, f, g):
     """Direct O(N^6) evaluation of Eq. (apndx_Qprojected) on the discrete
     Fourier coefficients: Qhat_k = sum_{l+m = k mod N} [G+(l,m) - G-(m)]
     fhat_l ghat_m, fhat = fft3(f)/N^3, then Q = beta Re(sum_k Qhat_k e^{...}).
+    With plan.nyquist_zero the G+ part runs over l and m off the Nyquist
+    planes only (no component equal to -N/2); G- over all pairs.
     Vectorised over l for each m.  Only sensible for N <= 8."""
     N = plan.N
     n3 = N ** 3
@@ -125,6 +154,10 @@ def collide_direct(plan, f, g):
     gh = gh.ravel()
     c = plan.c.ravel()
     b = plan.b.reshape(len(plan.rho), len(plan.sigma), n3)
+    if plan.nyquist_zero:
+        off_nyq = np.all(L3 != -(N // 2), axis=1).astype(float)
+    else:
+        off_nyq = np.ones(n3)
     Qh = np.zeros(n3, dtype=complex)
     for mi in range(n3):
         mvec = L3[mi]
@@ -136,18 +169,18 @@ def collide_direct(plan, f, g):
                 sg = plan.sigma[s]
                 ph = math.pi / plan.L * plan.rho[r] * ((aq * L3 - ap * mvec) @ sg)
                 Gp += plan.w_rho[r] * plan.w_sigma[s] * b[r, s, kidx] * np.exp(1j * ph)
-        contrib = (Gp - c[mi]) * fh * gh[mi]
+        contrib = (Gp * off_nyq * off_nyq[mi] - c[mi]) * fh * gh[mi]
         np.add.at(Qh, kidx, contrib)
     Q = dft.ifft3(Qh.reshape(N, N, N)) * n3
     return plan.beta * np.real(Q)
 
 
 def default_pair_plan(N, L, masses, p, q, omega, alpha, Nrho, sphere, M=None,
-                      R=None, beta=None, gamma=None, eta=None):
+                      R=None, beta=None, gamma=None, eta=None, nyquist_zero=False):
     """Convenience: PairPlan for species (p, q) with a named sphere set."""
     sigma, w = sphere_set(sphere, M)
     return PairPlan(N, L, masses[p], masses[q], omega, alpha, Nrho, sigma, w,
-                    R=R, beta=beta, gamma=gamma, eta=eta)
+                    R=R, beta=beta, gamma=gamma, eta=eta, nyquist_zero=nyquist_zero)
 
 
 def mixture_collision(pair_plans, F):

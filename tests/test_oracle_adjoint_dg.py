@@ -12,18 +12,19 @@ from oracle.collide import PairPlan, collide
 from oracle.quadrature import sphere_set
 
 
-def _plan(N, alpha=1.0, mp=1.0, mq=2.5):
+def _plan(N, alpha=1.0, mp=1.0, mq=2.5, nyquist_zero=False):
     s, w = sphere_set("icosahedron")
-    return PairPlan(N, 5.0, mp, mq, 0.7, alpha, 3, s, w, R=4.0)
+    return PairPlan(N, 5.0, mp, mq, 0.7, alpha, 3, s, w, R=4.0, nyquist_zero=nyquist_zero)
 
 
-@pytest.mark.parametrize("alpha", [1.0, 1.4])
-def test_vjp_equals_bruteforce_jacobian(alpha):
+@pytest.mark.parametrize("alpha,nyq", [(1.0, False), (1.4, False), (1.0, True), (1.4, True)])
+def test_vjp_equals_bruteforce_jacobian(alpha, nyq):
     """Q is linear in each argument, so the Jacobian's columns are Q(e_j, g)
-    and Q(f, e_j); the VJP must equal J^T wbar."""
+    and Q(f, e_j); the VJP must equal J^T wbar (also for the variant whose
+    gain drops the Nyquist planes)."""
     N = 4
     rng = np.random.default_rng(3)
-    pl = _plan(N, alpha)
+    pl = _plan(N, alpha, nyquist_zero=nyq)
     f, g, wb = rng.random((N,) * 3), rng.random((N,) * 3), rng.standard_normal((N,) * 3)
     n3 = N ** 3
     Jf = np.zeros((n3, n3))

@@ -28,6 +28,46 @@ def test_algorithm2_equals_direct_galerkin_sum(N, alpha, sphere):
     assert np.max(np.abs(Q1 - Q2)) <= 1e-13 * np.max(np.abs(Q1))
 
 
+@pytest.mark.parametrize("N,alpha,sphere", [(4, 1.0, "icosahedron"), (6, 1.0, "octahedron"),
+                                            (6, 1.4, "fibonacci")])
+def test_nyquist_zero_variant_equals_restricted_direct_sum(N, alpha, sphere):
+    """The variant whose gain is formed from Nyquist-zeroed transforms is the
+    Galerkin sum of Eq. (apndx_Qprojected) with G+ restricted to wave pairs
+    (l, m) that have no component equal to -N/2 (G- unrestricted).  The
+    inputs carry Nyquist content, and the variant differs from Algorithm 2
+    as it stands."""
+    rng = np.random.default_rng(N + 7)
+    s, w = sphere_set(sphere, 7 if sphere == "fibonacci" else None)
+    pl = PairPlan(N, 5.0, 1.0, 2.5, 0.7, alpha, 3, s, w, R=4.0, nyquist_zero=True)
+    pl0 = PairPlan(N, 5.0, 1.0, 2.5, 0.7, alpha, 3, s, w, R=4.0)
+    f, g = rng.random((N, N, N)), rng.random((N, N, N))
+    Q1, Q2 = collide(pl, f, g), collide_direct(pl, f, g)
+    assert np.max(np.abs(Q1 - Q2)) <= 1e-13 * np.max(np.abs(Q1))
+    assert np.max(np.abs(Q1 - collide(pl0, f, g))) > 1e-6 * np.max(np.abs(Q1))
+
+
+def test_nyquist_zero_variant_is_exact_on_band_limited_inputs():
+    """Inputs with no Nyquist content (their DFT vanishes wherever a wave
+    index is -N/2) are left unchanged by the mask, so the variant returns
+    Algorithm 2's result for them."""
+    from oracle import dft
+    N = 6
+    rng = np.random.default_rng(21)
+    s, w = sphere_set("icosahedron")
+    keep = np.ones(N)
+    keep[N // 2] = 0.0
+    mask = keep[:, None, None] * keep[None, :, None] * keep[None, None, :]
+
+    def band_limited():
+        return np.real(dft.ifft3(mask * dft.fft3(rng.random((N, N, N)))))
+    f, g = band_limited(), band_limited()
+    for mp, mq in ((1.0, 1.0), (1.0, 2.5)):
+        pl = PairPlan(N, 5.0, mp, mq, 0.7, 1.0, 3, s, w, R=4.0, nyquist_zero=True)
+        pl0 = PairPlan(N, 5.0, mp, mq, 0.7, 1.0, 3, s, w, R=4.0)
+        Q1, Q0 = collide(pl, f, g), collide(pl0, f, g)
+        assert np.max(np.abs(Q1 - Q0)) <= 1e-13 * np.max(np.abs(Q0))
+
+
 def test_kernel_mode_matches_continuous_vhs():
     """Eq. (realGG) for VHS reduces to a 1-D integral:
     G+(l,m) = int_0^R rho^{gamma+2} (4 pi)^2 sinc(pi/L rho a_q |l+m|)
@@ -175,17 +215,18 @@ def test_projection_restores_invariants():
     assert abs(np.sum((Q - Qt) * Z)) < 1e-10 * np.sqrt(np.sum(Q ** 2) * np.sum(Z ** 2))
 
 
-@pytest.mark.parametrize("sphere", ["octahedron", "icosahedron"])
-def test_gain_sum_symmetries_of_antipodal_sphere_sets(sphere):
+@pytest.mark.parametrize("sphere,nyq", [("octahedron", False), ("icosahedron", False),
+                                        ("icosahedron", True)])
+def test_gain_sum_symmetries_of_antipodal_sphere_sets(sphere, nyq):
     """Two exact identities of the gain sum of Algorithm 2 for a sphere set
     closed under sigma -> -sigma with equal weights, at every radius r:
     the m-sum of u1 * u2 of the pair (q, p) on (f^q, f^p) equals that of
     (p, q) on (f^p, f^q), and for p == q on one input the terms of sigma and
     -sigma coincide, so half of the set with doubled weights gives the sum.
     The GPU schedule relies on both; here they are checked term by term on
-    the oracle's own transforms."""
+    the oracle's own transforms, also with the Nyquist planes dropped."""
     from oracle import dft
-    from oracle.collide import phase_argument
+    from oracle.collide import nyquist_mask, phase_argument
     N, L = 6, 4.0
     sig, w = sphere_set(sphere)
     rng = np.random.default_rng(11)
@@ -196,6 +237,8 @@ def test_gain_sum_symmetries_of_antipodal_sphere_sets(sphere):
 
     def msum(pl, f, g, r, ms, scale=1.0):
         F, G = dft.fft3(f), dft.fft3(g)
+        if nyq:
+            F, G = nyquist_mask(N) * F, nyquist_mask(N) * G
         acc = np.zeros((N, N, N), complex)
         for m in ms:
             a = phase_argument(pl, r, m)
