@@ -89,6 +89,16 @@ typedef enum { DGFS_OP_COLLIDE = 0, DGFS_OP_VJP = 1, DGFS_OP_RHS = 2, DGFS_OP_ST
  *                  element); only used by dgfs_rhs/dgfs_step, 0 otherwise
  *   precision      DGFS_FP64, or DGFS_FP32_MIXED (FP32 transforms with
  *                  compensated FP32 accumulation; inputs/outputs stay FP64)
+ *   nyquist_zero   0: Algorithm 2 as it stands.  1: the gain's translates
+ *                  t1, t2 are formed from fft(f^p), fft(f^q) with their
+ *                  Nyquist planes (wave index -N/2 on any axis) set to zero;
+ *                  the loss term is unchanged.  Not in the paper: it changes
+ *                  Q by the Nyquist content of the inputs, which is at
+ *                  roundoff level for distributions supported well inside
+ *                  D_L.  t1 and t2 are then Hermitian, so u1 and u2 are real
+ *                  and the VHS gain evaluates both with one complex
+ *                  transform of t1 + i t2.  Applies to every entry point
+ *                  (dgfs_collide_vjp differentiates this operator).
  */
 #define DGFS_MAX_SPECIES 4
 typedef struct {
@@ -108,6 +118,7 @@ typedef struct {
   int32_t N_rho;
   int32_t dg_order;
   int32_t precision;
+  int32_t nyquist_zero;
 } dgfs_params;
 
 /* Builds the tables of Algorithm 1 for every ordered pair (host FP64, then

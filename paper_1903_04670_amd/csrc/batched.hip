@@ -76,8 +76,13 @@ __global__ void __launch_bounds__(64) kb_shift(const SubItem *items, const int *
   const SubItem &si = items[it];
   dispatch_N<NC>(si.N, [&](auto nn) {
     constexpr int NN = decltype(nn)::value;
-    const int pb = (NN * NN + 31) / 32;
-    shift_x_body<T, NN>(si.a, local % pb, (local / pb) % 2, local / (2 * pb), threadIdx.x);
+    if (si.a.pack && !si.vss) {
+      const int pb = (NN * (NN / 2) + 31) / 32;  // x-lines with k_z < N/2 (real-packed gain)
+      shift_x_body<T, NN, true>(si.a, local % pb, (local / pb) % 2, local / (2 * pb), threadIdx.x);
+    } else {
+      const int pb = (NN * NN + 31) / 32;
+      shift_x_body<T, NN>(si.a, local % pb, (local / pb) % 2, local / (2 * pb), threadIdx.x);
+    }
   });
 }
 
@@ -93,6 +98,7 @@ __global__ void __launch_bounds__(128) kb_gain_yz(const SubItem *items, const in
     // the phase rows follow the planes of the non-VSS body
     auto *phs = reinterpret_cast<C<T> *>(smem + (size_t)g_gain<NN>() * gain_bufs<T>() * NN * (NN + 1) * sizeof(C<T>));
     if (si.vss) gain_yz_vss_body<T, NN, g_gain<NN>()>(si.a, jx, r, e, threadIdx.x, lds, phs);
+    else if (si.a.pack) gain_yz_body<T, NN, g_gain<NN>(), 1, true>(si.a, jx, r, e, threadIdx.x, lds, phs);
     else gain_yz_body<T, NN, g_gain<NN>()>(si.a, jx, r, e, threadIdx.x, lds, phs);
   });
 }
@@ -127,7 +133,7 @@ static int blocks_of(int stage, const SubItem &s) {
   const int gs = 64 / N > 0 ? 64 / N : 1, te = N >= 48 ? 1 : 2;
   switch (stage) {
     case kFwd: return (N * s.fw.n_nodes * s.fw.nz + gs - 1) / gs;
-    case kShift: return pb * 2 * E;
+    case kShift: return (s.a.pack && !s.vss ? (N * (N / 2) + 31) / 32 : pb) * 2 * E;
     case kGainYZ: return N * s.a.Nr * E;
     case kGainX: return s.vss ? pb * ((E + te - 1) / te) : pb * E;
     default: {

@@ -36,15 +36,29 @@ static hipError_t launch_pipeline_N(const PipeArgs &a, const FwdArgs &fw, const 
     DGFS_LAUNCH("k_fwd_yz", (k_fwd_yz<T, N, G>), dim3((planes + G - 1) / G), dim3(G * N), 0, st, fw);
   }
   const int pb2 = (N * N + 31) / 32;  // lane pairs: 32 x-lines per 64-thread block
-  switch (shift_split<T>()) {
-    case 1: DGFS_LAUNCH("k_shift_x", (k_shift_x<T, N, 1>), dim3(pb2, 2, EG), dim3(64), 0, st, a); break;
-    case 4: DGFS_LAUNCH("k_shift_x", (k_shift_x<T, N, 4>), dim3(pb2, 8, EG), dim3(64), 0, st, a); break;
-    case 8: DGFS_LAUNCH("k_shift_x", (k_shift_x<T, N, 8>), dim3(pb2, 16, EG), dim3(64), 0, st, a); break;
-    default: DGFS_LAUNCH("k_shift_x", (k_shift_x<T, N, 2>), dim3(pb2, 4, EG), dim3(64), 0, st, a); break;
+  if (a.pack && !vss) {
+    // real-packed gain: the x-lines with k_z < N/2 only
+    const int pbh = (N * (N / 2) + 31) / 32;
+    switch (shift_split<T>()) {
+      case 1: DGFS_LAUNCH("k_shift_x", (k_shift_x<T, N, 1, true>), dim3(pbh, 2, EG), dim3(64), 0, st, a); break;
+      case 4: DGFS_LAUNCH("k_shift_x", (k_shift_x<T, N, 4, true>), dim3(pbh, 8, EG), dim3(64), 0, st, a); break;
+      case 8: DGFS_LAUNCH("k_shift_x", (k_shift_x<T, N, 8, true>), dim3(pbh, 16, EG), dim3(64), 0, st, a); break;
+      default: DGFS_LAUNCH("k_shift_x", (k_shift_x<T, N, 2, true>), dim3(pbh, 4, EG), dim3(64), 0, st, a); break;
+    }
+  } else {
+    switch (shift_split<T>()) {
+      case 1: DGFS_LAUNCH("k_shift_x", (k_shift_x<T, N, 1>), dim3(pb2, 2, EG), dim3(64), 0, st, a); break;
+      case 4: DGFS_LAUNCH("k_shift_x", (k_shift_x<T, N, 4>), dim3(pb2, 8, EG), dim3(64), 0, st, a); break;
+      case 8: DGFS_LAUNCH("k_shift_x", (k_shift_x<T, N, 8>), dim3(pb2, 16, EG), dim3(64), 0, st, a); break;
+      default: DGFS_LAUNCH("k_shift_x", (k_shift_x<T, N, 2>), dim3(pb2, 4, EG), dim3(64), 0, st, a); break;
+    }
   }
   constexpr int GG = gain_groups<N>();
   if (!vss) {
-    DGFS_LAUNCH("k_gain_yz", (k_gain_yz<T, N, GG>), dim3(N, a.Nr, EG), dim3(GG * 2 * N), 0, st, a);
+    if (a.pack)
+      DGFS_LAUNCH("k_gain_yz", (k_gain_yz<T, N, GG, 1, true>), dim3(N, a.Nr, EG), dim3(GG * 2 * N), 0, st, a);
+    else
+      DGFS_LAUNCH("k_gain_yz", (k_gain_yz<T, N, GG>), dim3(N, a.Nr, EG), dim3(GG * 2 * N), 0, st, a);
     DGFS_LAUNCH("k_gain_x", (k_gain_x<T, N, sizeof(T) == 4>), dim3(pb2, sizeof(T) == 4 ? EG : E), dim3(64), 0, st, a);
   } else {
     constexpr int TE = N >= 48 ? 1 : 2;
@@ -174,6 +188,7 @@ void pipeline_common(const dgfs_plan_s *pl, PipeArgs &a) {
   a.gs_half = pl->gs_half_dev;
   a.gs_T_full = pl->gs_T_full;
   a.gs_T_half = pl->gs_T_half;
+  a.pack = pl->nyquist_zero && pl->vhs ? 1 : 0;
 }
 
 }  // namespace dgfs

@@ -58,6 +58,9 @@ struct PipeArgs {
   // entries m | first << 16 or -1), for the full and the half set
   const int *gs_full, *gs_half;
   int gs_T_full, gs_T_half;
+  // 1: the plan drops the Nyquist planes from the gain's translates (its
+  // twiddle tables are zero there), so k_gain_yz takes the real-packed path
+  int pack;
   void *Z, *X, *Cb, *V;
 };
 
@@ -124,10 +127,11 @@ __device__ __forceinline__ const V *wave_uniform(const V *ptr) {
 // and 2n + 1 differ by one, N/2 being even) turns the 16 per-lane table
 // loads into scalar loads of ph_y(2n), and only zph ph_y(1)^p is per lane.
 // Per-lane loads that each wait for the previous one are what this avoids.
-template <typename T, int N>
+// A table with its Nyquist entry zeroed breaks the identity: SCALAR = false.
+template <typename T, int N, bool SCALAR = true>
 __device__ __forceinline__ void apply_col_phase(cplx<T> (&h)[N / 2], const cplx<T> *ph, int c, int p) {
   const cplx<T> zph = gload(ph, N + c);
-  if constexpr (2 * N == 64) {
+  if constexpr (2 * N == 64 && SCALAR) {
     const cplx<T> *phu = wave_uniform(ph);
     const cplx<T> z1 = cmul(zph, uload(phu, 1));
     const cplx<T> L{p ? z1.x : zph.x, p ? z1.y : zph.y};
@@ -231,13 +235,19 @@ __global__ void __launch_bounds__(G * N) k_fwd_yz(FwdArgs a) {
 // transform of Z (decimation in time: lane p loads x = 2n + p and ends with
 // frequencies p*N/2 + k), then for every r and distinct sigma_x the phase
 // and the inverse transform (decimation in frequency back to x = 2n + p).
-template <typename T, int N>
+// HALF (real-packed plans): the x-lines with k_z in [0, N/2) only.  With the
+// Nyquist planes dropped, every X plane is the (k_y, k_z) spectrum of a real
+// function, so X(k_y, k_z) = conj X(-k_y, -k_z) and the gain kernel rebuilds
+// the columns k_z > N/2 from these; the Nyquist column k_z = N/2 has zero
+// twiddles and is never needed.
+template <typename T, int N, bool HALF = false>
 __device__ __forceinline__ void shift_x_body(const PipeArgs &a, int bx, int side, int e, int tid, int part = 0,
                                              int nparts = 1) {
   constexpr int H = N / 2;
   const int pencil = bx * 32 + (tid >> 1), p = tid & 1;
-  const bool valid = pencil < N * N;
-  const int pc = valid ? pencil : 0;  // idle lanes still take part in the lane swaps
+  const bool valid = pencil < (HALF ? N * H : N * N);
+  // idle lanes still take part in the lane swaps
+  const int pc = !valid ? 0 : HALF ? (pencil / H) * N + pencil % H : pencil;
   const int node = e / a.n_pairs, slot = e % a.n_pairs;
   const PairDev pd = a.pairs[a.pair_id[slot]];
   const size_t n3 = (size_t)N * N * N;
@@ -271,9 +281,10 @@ __device__ __forceinline__ void shift_x_body(const PipeArgs &a, int bx, int side
 // blockIdx.y = side + 2 part: the (r, s) loop is split over NP blocks per
 // (x-lines, side, eval), each redoing the cheap forward x transform, so that
 // more waves share the latency of the phase loads and stores
-template <typename T, int N, int NP = 1>
+template <typename T, int N, int NP = 1, bool HALF = false>
 __global__ void __launch_bounds__(64) k_shift_x(PipeArgs a) {
-  shift_x_body<T, N>(a, blockIdx.x, blockIdx.y & 1, gain_eval(a, blockIdx.z), threadIdx.x, blockIdx.y >> 1, NP);
+  shift_x_body<T, N, HALF>(a, blockIdx.x, blockIdx.y & 1, gain_eval(a, blockIdx.z), threadIdx.x, blockIdx.y >> 1,
+                           NP);
 }
 
 // ------------------------------------------------------------------ k_gain_yz
@@ -294,7 +305,7 @@ template <typename T> constexpr int gain_bufs() { return sizeof(T) == 4 ? 2 : 1;
 // current direction, [2 sides][2N] (y phases, then z phases).
 template <typename T, int N, int G> constexpr size_t gain_phase_elems() { return (size_t)G * 4 * N; }
 
-template <typename T, int N, int G, int NB = gain_bufs<T>()>
+template <typename T, int N, int G, int NB = gain_bufs<T>(), bool PACK = false>
 __device__ __forceinline__ void gain_yz_body(const PipeArgs &a, int jx, int r, int e, int tid, C<T> (*lds)[N][N + 1],
                                              C<T> *phs_all) {
   constexpr int H = N / 2;
@@ -371,7 +382,81 @@ __device__ __forceinline__ void gain_yz_body(const PipeArgs &a, int jx, int r, i
   const int Mx = a.half[slot] ? a.Mh : a.M;
   const int *mo = a.half[slot] ? a.mhalf : a.morder;
   const int iters = (Mx + G - 1) / G;
-  if constexpr (NB == 2 && 2 * N == 64) {
+  if constexpr (PACK) {
+    // Real-packed terms.  With the Nyquist planes dropped from both
+    // translates, u1 and u2 are real, so one column and one row transform of
+    // h = t1 + i t2 give u1 = Re h and u2 = Im h (t1 carrying w_m), and the
+    // product accumulates into the real parts of P.  The phase rows of the
+    // next direction are staged while the row pass runs, so two group
+    // barriers per direction suffice.
+    // X holds the columns k_z < N/2 only (shift_x_body<HALF>): a lane of
+    // column c > N/2 reads column N - c at the mirrored rows -y mod N and
+    // conjugates; the lane of the Nyquist column reads column 0, which its
+    // zero twiddle discards.
+    const bool mr = c > H;
+    const int col = c < H ? c : (c == H ? 0 : N - c);
+    const int rbase = (mr ? N - p : p) * N, rstep = mr ? -2 * N : 2 * N;
+    const int row0 = mr ? (p ? N - 1 : 0) : p;
+    const T csg = mr ? (T)-1 : (T)1;
+    auto load_half = [&](int side, int s, C<T>(&h)[H]) {
+      const C<T> *src = x_plane(a, X, slot, side, r, s, n3) + (size_t)jx * N * N + col;
+#pragma unroll
+      for (int n = 0; n < H; ++n) {
+        const C<T> v = src[n == 0 ? row0 * N : rbase + n * rstep];
+        h[n] = C<T>{v.x, csg * v.y};
+      }
+    };
+    int mi = g;
+    bool active = in_group && mi < Mx;
+    if (active) {
+      fetch_ph(mo[mi]);
+      stage_ph(mo[mi]);
+      if (mi + G < Mx) fetch_ph(mo[mi + G]);
+    }
+    group_sync<N>();
+    for (int it = 0; it < iters; ++it) {
+      if (active) {
+        const int s = a.sidx[mo[mi]];
+        C<T> h[H], h1[H];
+        load_half(0, s, h);
+        load_half(1, s, h1);
+        const C<T> z0 = phs[N + c], z1 = phs[3 * N + c];
+#pragma unroll
+        for (int n = 0; n < H; ++n) {
+          const C<T> t1 = cmul(h[n], cmul(phs[2 * n + p], z0));
+          const C<T> t2 = cmul(h1[n], cmul(phs[2 * N + 2 * n + p], z1));
+          h[n] = C<T>{t1.x - t2.y, t1.y + t2.x};
+        }
+        fft_pair<N, +1>(h, p);
+#pragma unroll
+        for (int k = 0; k < H; ++k) lds[NB * g][p * H + k][c] = h[k];
+      }
+      group_sync<N>();
+      const int mn = mi + G;
+      const bool next = in_group && mn < Mx;
+      if (next) {
+        stage_ph(mo[mn]);
+        if (mn + G < Mx) fetch_ph(mo[mn + G]);
+      }
+      if (active) {
+        C<T> h[H];
+#pragma unroll
+        for (int n = 0; n < H; ++n) h[n] = lds[NB * g][c][2 * n + p];
+        fft_pair<N, +1>(h, p);
+#pragma unroll
+        for (int k = 0; k < H; ++k) {
+          if constexpr (sizeof(T) == 4) {
+            acc_add(P[k].x, Pcx[k], h[k].x * h[k].y);
+          } else {
+            P[k].x += h[k].x * h[k].y;
+          }
+        }
+      }
+      group_sync<N>();
+      mi = mn;
+      active = next;
+    }
+  } else if constexpr (NB == 2 && 2 * N == 64) {
     // Terms from the plan's schedule: directions sharing (sigma_x, sigma_y)
     // have the same y phases, and the z phase is constant along a column, so
     // one column pass per side (y phases only) serves every direction of the
@@ -519,11 +604,11 @@ __device__ __forceinline__ void gain_yz_body(const PipeArgs &a, int jx, int r, i
     for (int k = 0; k < H; ++k) dst[(p * H + k) * N + c] = h[k];
   }
 }
-template <typename T, int N, int G, int NB = gain_bufs<T>()>
+template <typename T, int N, int G, int NB = gain_bufs<T>(), bool PACK = false>
 __global__ void __launch_bounds__(G * 2 * N) k_gain_yz(PipeArgs a) {
   __shared__ C<T> lds[G * NB][N][N + 1];
   __shared__ C<T> phs[gain_phase_elems<T, N, G>()];
-  gain_yz_body<T, N, G, NB>(a, blockIdx.x, blockIdx.y, gain_eval(a, blockIdx.z), threadIdx.x, lds, phs);
+  gain_yz_body<T, N, G, NB, PACK>(a, blockIdx.x, blockIdx.y, gain_eval(a, blockIdx.z), threadIdx.x, lds, phs);
 }
 
 // ------------------------------------------------------------------ k_gain_x

@@ -40,6 +40,7 @@ struct dgfs_plan_s {
   std::vector<double> sx_val;  // [Sx]
   std::vector<int> sx_idx;     // [M]
   std::vector<dgfs::PairHost> pairs;  // [ns*ns], p-major
+  bool nyquist_zero = false;  // gain translates drop the Nyquist planes (real-packed VHS gain)
   bool vhs = true;      // every pair has alpha == 1 (sigma-independent gain table)
   int chunk_evals = 0;  // evaluations per launch chosen by dgfs_autotune or its cache (0 = default)
   void *vss_dev = nullptr;  // VSS gain tables of all pairs (separate allocation)

@@ -136,6 +136,7 @@ extern "C" dgfs_status dgfs_plan_create(const dgfs_params *prm, dgfs_plan *out) 
   if (prm->N_rho < 1) { set_error("N_rho = %d must be >= 1", prm->N_rho); return DGFS_EINVAL; }
   if (prm->dg_order < 0 || prm->dg_order > 8) { set_error("dg_order = %d outside [0, 8]", prm->dg_order); return DGFS_EINVAL; }
   if (prm->precision != DGFS_FP64 && prm->precision != DGFS_FP32_MIXED) { set_error("unknown precision %d", prm->precision); return DGFS_EINVAL; }
+  if (prm->nyquist_zero != 0 && prm->nyquist_zero != 1) { set_error("nyquist_zero = %d must be 0 or 1", prm->nyquist_zero); return DGFS_EINVAL; }
   for (int p = 0; p < ns; ++p)
     if (!(prm->mass[p] > 0.0)) { set_error("mass[%d] must be > 0", p); return DGFS_EINVAL; }
   for (int i = 0; i < ns * ns; ++i) {
@@ -157,6 +158,7 @@ extern "C" dgfs_status dgfs_plan_create(const dgfs_params *prm, dgfs_plan *out) 
   pl->Nr = prm->N_rho;
   pl->P = prm->dg_order;
   pl->precision = prm->precision;
+  pl->nyquist_zero = prm->nyquist_zero != 0;
   pl->L = prm->L;
   pl->S = prm->S;
   pl->mass.assign(prm->mass, prm->mass + ns);
@@ -230,16 +232,20 @@ extern "C" dgfs_status dgfs_plan_create(const dgfs_params *prm, dgfs_plan *out) 
           for (int j = 0; j < N; ++j) {
             double a = th * pl->sx_val[s] * wave(j, N);
             size_t o = off_px[pr] + 2 * ((((size_t)side * Nr + r) * Sx + s) * N + j);
-            hostbuf[o] = std::cos(a) / n3;
-            hostbuf[o + 1] = std::sin(a) / n3;
+            // with nyquist_zero the twiddle is 0 on the Nyquist plane of its
+            // axis: the three axes' zeros together mask fft(f) as required
+            const double keep = pl->nyquist_zero && j == N / 2 ? 0.0 : 1.0;
+            hostbuf[o] = keep * std::cos(a) / n3;
+            hostbuf[o + 1] = keep * std::sin(a) / n3;
           }
         for (int m = 0; m < M; ++m)
           for (int ax = 0; ax < 2; ++ax)
             for (int j = 0; j < N; ++j) {
               double a = th * pl->sigma[3 * m + 1 + ax] * wave(j, N);
               size_t o = off_pyz[pr] + 2 * (((((size_t)side * Nr + r) * M + m) * 2 + ax) * N + j);
-              hostbuf[o] = std::cos(a);
-              hostbuf[o + 1] = std::sin(a);
+              const double keep = pl->nyquist_zero && j == N / 2 ? 0.0 : 1.0;
+              hostbuf[o] = keep * std::cos(a);
+              hostbuf[o + 1] = keep * std::sin(a);
             }
       }
     // VHS gain table: b_r(k) = rho_r^{gamma+2} 4 pi sinc(pi/L rho_r a_q |k|) (Eq. Fkr_vss with alpha = 1)

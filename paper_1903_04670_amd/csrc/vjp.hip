@@ -47,7 +47,10 @@ static hipError_t launch_vjp_N(const VjpArgs &v, const FwdArgs &fw, hipStream_t 
   const int pb2 = (N * N + 31) / 32;  // lane pairs: 32 x-lines per 64-thread block
   DGFS_LAUNCH("k_vjp_v", (k_vjp_v<T, N>), dim3(pb2, E), dim3(64), 0, st, v);
   constexpr int GV = 128 / (2 * N) > 0 ? 128 / (2 * N) : 1;  // groups per block, as the plan's VJP schedule
-  DGFS_LAUNCH("k_vjp_yz", (k_vjp_yz<T, N, GV>), dim3(N, a.Nr, E), dim3(GV * 2 * N), 0, st, v);
+  if (a.pack)
+    DGFS_LAUNCH("k_vjp_yz", (k_vjp_yz<T, N, GV, false>), dim3(N, a.Nr, E), dim3(GV * 2 * N), 0, st, v);
+  else
+    DGFS_LAUNCH("k_vjp_yz", (k_vjp_yz<T, N, GV>), dim3(N, a.Nr, E), dim3(GV * 2 * N), 0, st, v);
   if (v.sym)
     DGFS_LAUNCH("k_vjp_x", (k_vjp_x<T, N, true>), dim3(pb2, E), dim3(64), 0, st, v);
   else

@@ -122,7 +122,9 @@ __global__ void __launch_bounds__(64) k_vjp_v(VjpArgs v) {
 // w_m u v, iFFT_z back into the same LDS slots, iFFT_y of the columns, the
 // yz phases of `side`, and accumulation; the last term of a (sigma_x group,
 // side) unit writes Y_side[r][s] for the plane.
-template <typename T, int N, int G>
+// SCALAR = false for plans whose twiddle tables have zeroed Nyquist entries
+// (the scalar-phase identities of the N = 32 path do not hold for them).
+template <typename T, int N, int G, bool SCALAR = true>
 __global__ void __launch_bounds__(G * 2 * N) k_vjp_yz(VjpArgs v) {
   constexpr int H = N / 2;
   const PipeArgs &a = v.a;
@@ -175,7 +177,7 @@ __global__ void __launch_bounds__(G * 2 * N) k_vjp_yz(VjpArgs v) {
       C<T> h[H];
 #pragma unroll
       for (int n = 0; n < H; ++n) h[n] = src[(2 * n + p) * N + c];
-      apply_col_phase<T, N>(h, pyz + (((size_t)uside * a.Nr + r) * a.M + m) * 2 * N, c, p);
+      apply_col_phase<T, N, SCALAR>(h, pyz + (((size_t)uside * a.Nr + r) * a.M + m) * 2 * N, c, p);
       fft_pair<N, +1>(h, p);
 #pragma unroll
       for (int k = 0; k < H; ++k) buf[p * H + k][c] = h[k];
@@ -201,7 +203,7 @@ __global__ void __launch_bounds__(G * 2 * N) k_vjp_yz(VjpArgs v) {
       fft_pair<N, +1>(h, p);  // column z = c, y = pH + k
       const C<T> *ph = pyz + (((size_t)side * a.Nr + r) * a.M + m) * 2 * N;
       const C<T> zph = gload(ph, N + c);
-      if constexpr (2 * N == 64) {
+      if constexpr (2 * N == 64 && SCALAR) {
         // rows y = pH + k: ph_y(pH + k) = ph_y(k) ph_y(H)^p (wave numbers k and k - H)
         const C<T> *phu = wave_uniform(ph);
         const C<T> zH = cmul(zph, uload(phu, H));

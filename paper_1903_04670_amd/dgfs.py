@@ -31,7 +31,7 @@ class Params(ct.Structure):
     _fields_ = [("n_species", ct.c_int32), ("mass", _dp), ("omega", _dp), ("alpha", _dp),
                 ("beta", _dp), ("kn", _dp), ("N", ct.c_int32), ("L", ct.c_double), ("S", ct.c_double),
                 ("R", _dp), ("M", ct.c_int32), ("sigma", _dp), ("w_sigma", _dp), ("N_rho", ct.c_int32),
-                ("dg_order", ct.c_int32), ("precision", ct.c_int32)]
+                ("dg_order", ct.c_int32), ("precision", ct.c_int32), ("nyquist_zero", ct.c_int32)]
 
 
 class Mesh(ct.Structure):
@@ -135,10 +135,12 @@ class Plan:
 
     Arguments mirror dgfs_params: masses [ns], omega/alpha [ns, ns],
     N, L, S, sphere (name) or sigma/w_sigma, M, Nrho, optional R/beta/kn
-    [ns, ns], dg_order, precision 'fp64' | 'fp32'."""
+    [ns, ns], dg_order, precision 'fp64' | 'fp32', nyquist_zero (drop the
+    Nyquist planes from the gain's translates; not in the paper)."""
 
     def __init__(self, masses, omega, alpha, N, L, Nrho, sphere="icosahedron", M=None, S=0.0,
-                 sigma=None, w_sigma=None, R=None, beta=None, kn=None, dg_order=0, precision="fp64"):
+                 sigma=None, w_sigma=None, R=None, beta=None, kn=None, dg_order=0, precision="fp64",
+                 nyquist_zero=False):
         ns = len(masses)
         self.ns, self.N, self.L, self.Nrho = ns, int(N), float(L), int(Nrho)
         self.masses = [float(m) for m in masses]
@@ -149,6 +151,7 @@ class Plan:
         self.M = len(self.w_sigma)
         self.precision = {"fp64": FP64, "fp32": FP32_MIXED}[precision]
         self.dg_order = int(dg_order)
+        self.nyquist_zero = bool(nyquist_zero)
         keep = []
 
         def ptr(a, n):
@@ -175,6 +178,7 @@ class Plan:
         p.N_rho = self.Nrho
         p.dg_order = self.dg_order
         p.precision = self.precision
+        p.nyquist_zero = int(self.nyquist_zero)
         h = _vp()
         _check(lib.dgfs_plan_create(ct.byref(p), ct.byref(h)), "dgfs_plan_create")
         self.handle = h

@@ -6,7 +6,7 @@ from oracle.collide import PairPlan
 from oracle.quadrature import sphere_set
 
 
-def oracle_pairs(cfg, gamma=None, eta=None, beta=None):
+def oracle_pairs(cfg, gamma=None, eta=None, beta=None, nyquist_zero=False):
     ns = cfg["ns"]
     s, w = sphere_set(cfg["sphere"], cfg["M"])
     plans = [[None] * ns for _ in range(ns)]
@@ -15,15 +15,16 @@ def oracle_pairs(cfg, gamma=None, eta=None, beta=None):
             plans[p][q] = PairPlan(cfg["N"], cfg["L"], cfg["masses"][p], cfg["masses"][q],
                                    cfg["omega"][p][q], cfg["alpha"][p][q], cfg["Nrho"], s, w,
                                    R=cfg["R"][p][q], gamma=gamma, eta=eta,
-                                   beta=None if beta is None else beta[p][q])
+                                   beta=None if beta is None else beta[p][q],
+                                   nyquist_zero=nyquist_zero)
     return plans
 
 
-def gpu_plan(cfg, precision="fp64", dg_order=0, beta=None):
+def gpu_plan(cfg, precision="fp64", dg_order=0, beta=None, nyquist_zero=False):
     from paper_1903_04670_amd import dgfs
     return dgfs.Plan(cfg["masses"], cfg["omega"], cfg["alpha"], cfg["N"], cfg["L"], cfg["Nrho"],
                      sphere=cfg["sphere"], M=cfg["M"], S=cfg["S"], R=cfg["R"], beta=beta,
-                     dg_order=dg_order, precision=precision)
+                     dg_order=dg_order, precision=precision, nyquist_zero=nyquist_zero)
 
 
 def rel_linf(a, b):

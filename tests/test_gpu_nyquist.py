@@ -1,0 +1,166 @@
+"""GPU parity of the variant whose gain drops the Nyquist planes of fft(f^p)
+and fft(f^q) (plan option nyquist_zero; the real-packed VHS gain kernel),
+against the oracle's variant of the same operator.
+
+Bar: relative L-infinity error <= 1e-11 in FP64, as for Algorithm 2.  The
+inputs carry Nyquist content (5 % pointwise noise), and each test also checks
+that the result differs from Algorithm 2's by more than the bar, so a plan
+that ignored the option would fail.
+"""
+import numpy as np
+import pytest
+
+from helpers import gpu_plan, oracle_pairs, rel_linf, small_config
+from oracle.adjoint import collide_vjp as oracle_vjp
+from oracle.collide import collide as oracle_collide
+from oracle.collide import mixture_collision
+from paper_1903_04670_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-11
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _collide(torch, plan, F, p, q):
+    from paper_1903_04670_amd import dgfs
+    Fd = torch.from_numpy(F).cuda()
+    out = dgfs.collide(plan, p, q, Fd[:, p], Fd[:, q])
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+@pytest.mark.parametrize("N,kind", [(4, "octahedron"), (6, "icosahedron"), (8, "fibonacci"),
+                                    (12, "icosahedron"), (16, "octahedron"), (18, "icosahedron"),
+                                    (24, "octahedron"), (36, "icosahedron"), (48, "octahedron")])
+def test_packed_gain_small_sizes_all_pairs(torch_cuda, N, kind):
+    cfg = small_config(N, ns=2, M_kind=kind, Nrho=3 if N < 16 else 4, seed=60 + N, n_nodes=2)
+    opl = oracle_pairs(cfg, nyquist_zero=True)
+    lit = oracle_pairs(cfg)
+    pl = gpu_plan(cfg, nyquist_zero=True)
+    for p in range(2):
+        for q in range(2):
+            got = _collide(torch_cuda, pl, cfg["F"], p, q)
+            for i in range(cfg["n_nodes"]):
+                ref = oracle_collide(opl[p][q], cfg["F"][i, p], cfg["F"][i, q])
+                assert rel_linf(got[i], ref) <= TOL, (N, p, q, i)
+            ref0 = oracle_collide(lit[p][q], cfg["F"][0, p], cfg["F"][0, q])
+            assert rel_linf(got[0], ref0) > 10 * TOL, (N, p, q)
+
+
+def test_packed_gain_couette_N32_all_pairs(torch_cuda):
+    """N = 32, icosahedron M = 12, N_rho = 16, two species, one node."""
+    cfg = wl.couette_two_species(K=1, P=0)
+    opl = oracle_pairs(cfg, nyquist_zero=True)
+    pl = gpu_plan(cfg, nyquist_zero=True)
+    for p in range(2):
+        for q in range(2):
+            got = _collide(torch_cuda, pl, cfg["F"], p, q)
+            ref = oracle_collide(opl[p][q], cfg["F"][0, p], cfg["F"][0, q])
+            err = rel_linf(got[0], ref)
+            print("nyquist-zero N=32 (%d,%d): rel Linf %.3e" % (p, q, err))
+            assert err <= TOL, (p, q)
+
+
+@pytest.mark.parametrize("sphere", ["icosahedron", "octahedron"])
+def test_packed_gain_symmetric_schedule_three_species(torch_cuda, sphere, monkeypatch):
+    """Mixture collision term of three species through dgfs_rhs (mirrored
+    (q, p) sums, half-set (p, p) sums, one pair with R_pq != R_qp), against
+    the oracle and against the schedule with the reuse turned off."""
+    from paper_1903_04670_amd import dgfs
+    torch = torch_cuda
+    cfg = small_config(16, ns=3, M_kind=sphere, Nrho=3, seed=61, n_nodes=3)
+    R = cfg["R"].copy()
+    R[0, 2] *= 0.9
+    cfg["R"] = R
+    ref = mixture_collision(oracle_pairs(cfg, nyquist_zero=True), cfg["F"])
+    pl = gpu_plan(cfg, nyquist_zero=True)
+    F = torch.from_numpy(cfg["F"]).cuda()
+    got = dgfs.rhs(pl, F).cpu().numpy()
+    assert rel_linf(got, ref) <= TOL
+    monkeypatch.setenv("DGFS_NO_SYMMETRY", "1")
+    full = dgfs.rhs(pl, F).cpu().numpy()
+    assert rel_linf(full, ref) <= TOL
+
+
+def test_packed_gain_fp32_mixed_error_bound(torch_cuda):
+    """FP32 transforms: the packed transform carries u1 and u2 in one
+    complex array, so each picks up the rounding of the other; the bounds of
+    the literal FP32-mixed path still hold (2e-6 against the loss term,
+    5e-4 against Q)."""
+    from oracle.collide import collide_gain_loss
+    cfg = wl.couette_two_species(K=1, P=0)
+    opl = oracle_pairs(cfg, nyquist_zero=True)
+    pl = gpu_plan(cfg, precision="fp32", nyquist_zero=True)
+    for p, q in [(0, 1), (1, 1)]:
+        got = _collide(torch_cuda, pl, cfg["F"], p, q)
+        gain, loss = collide_gain_loss(opl[p][q], cfg["F"][0, p], cfg["F"][0, q])
+        ref = gain - loss
+        err_q = rel_linf(got[0], ref)
+        err_l = float(np.max(np.abs(got[0] - ref)) / np.max(np.abs(loss)))
+        print("nyquist-zero fp32-mixed (%d,%d): rel to |Q| %.3e, rel to |loss| %.3e" % (p, q, err_q, err_l))
+        assert err_l <= 2e-6
+        assert err_q <= 5e-4
+
+
+@pytest.mark.parametrize("N,kind", [(8, "icosahedron"), (32, "icosahedron")])
+def test_vjp_of_the_variant(torch_cuda, N, kind):
+    """The adjoint differentiates the variant (its N = 32 column phases take
+    the per-lane path, the scalar identity not holding for zeroed rows)."""
+    from paper_1903_04670_amd import dgfs
+    torch = torch_cuda
+    cfg = small_config(N, ns=2, M_kind=kind, Nrho=4 if N < 32 else 3, seed=70 + N, n_nodes=1)
+    W = np.random.default_rng(N).standard_normal((1, N, N, N))
+    opl = oracle_pairs(cfg, nyquist_zero=True)
+    pl = gpu_plan(cfg, nyquist_zero=True)
+    F = torch.from_numpy(cfg["F"]).cuda()
+    Wd = torch.from_numpy(W).cuda()
+    for p, q in [(0, 1), (1, 1)]:
+        gf, gq = dgfs.collide_vjp(pl, p, q, F[:, p], F[:, q], Wd)
+        torch.cuda.synchronize()
+        rf, rq = oracle_vjp(opl[p][q], cfg["F"][0, p], cfg["F"][0, q], W[0])
+        assert rel_linf(gf[0].cpu().numpy(), rf) <= TOL, (N, p, q)
+        assert rel_linf(gq[0].cpu().numpy(), rq) <= TOL, (N, p, q)
+
+
+def test_vss_plan_with_the_variant(torch_cuda):
+    """A VSS plan (alpha != 1) honours the option through its zeroed twiddle
+    tables (its gain kernel is not packed)."""
+    cfg = small_config(8, ns=2, M_kind="fibonacci", Nrho=4, seed=72, n_nodes=2)
+    cfg["alpha"] = np.full((2, 2), 1.4)
+    opl = oracle_pairs(cfg, nyquist_zero=True)
+    pl = gpu_plan(cfg, nyquist_zero=True)
+    for p, q in [(0, 1), (1, 1)]:
+        got = _collide(torch_cuda, pl, cfg["F"], p, q)
+        for i in range(2):
+            ref = oracle_collide(opl[p][q], cfg["F"][i, p], cfg["F"][i, q])
+            assert rel_linf(got[i], ref) <= TOL, (p, q, i)
+
+
+def test_batched_with_the_variant_equals_single_calls(torch_cuda):
+    """Instances with and without the option (N 16, 24, 32) in one batched
+    launch, bit-identical to one dgfs_collide call per item."""
+    from paper_1903_04670_amd import dgfs
+    torch = torch_cuda
+    plans, items, outs_b, outs_s = [], [], [], []
+    for k, (N, nyq) in enumerate([(16, True), (24, False), (32, True), (24, True)]):
+        cfg = small_config(N, ns=2, Nrho=3, seed=80 + k, n_nodes=2)
+        pl = gpu_plan(cfg, nyquist_zero=nyq)
+        plans.append(pl)
+        F = torch.from_numpy(cfg["F"]).cuda()
+        for p in range(2):
+            for q in range(2):
+                ob = torch.zeros(F[:, p].shape, dtype=torch.float64, device="cuda")
+                items.append((k, p, q, F[:, p], F[:, q], ob))
+                outs_b.append(ob)
+                outs_s.append(dgfs.collide(pl, p, q, F[:, p], F[:, q]))
+    dgfs.collide_batched(plans, items)
+    torch.cuda.synchronize()
+    for ob, os_ in zip(outs_b, outs_s):
+        assert torch.equal(ob, os_)
