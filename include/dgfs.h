@@ -76,7 +76,9 @@ typedef enum { DGFS_OP_COLLIDE = 0, DGFS_OP_VJP = 1, DGFS_OP_RHS = 2, DGFS_OP_ST
  *                  NULL together with beta == NULL => unit reduced Knudsen
  *                  number, beta = mu^{1/2-omega} alpha/(2^{1+alpha}
  *                  Gamma(5/2-omega) pi), mu = m_p m_q/(m_p+m_q)
- *   N              velocity points per axis (even, 2^a 3^b, 4 <= N <= 48)
+ *   N              velocity points per axis: 4, 6, 8, 10, 12, 14, 16, 18, 24,
+ *                  32, 36, 40, 48 or 56 (dgfs_collide_batched: N <= 48 and
+ *                  N = 2^a 3^b)
  *   L              velocity box half-width: D_L = [-L, L]^3
  *   S              support radius of f (informational; R defaults from L)
  *   R[ns*ns]       truncation radius of the relative-velocity ball; NULL =>

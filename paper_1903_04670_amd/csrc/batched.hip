@@ -181,6 +181,10 @@ static dgfs_status plan_batch(const dgfs_plan *plans, int32_t n_plans, const dgf
     const dgfs_plan_s *pl = plans[it.plan];
     if (it.p < 0 || it.q < 0 || it.p >= pl->ns || it.q >= pl->ns) { set_error("item %lld: species out of range", (long long)i); return DGFS_EINVAL; }
     if (it.n_nodes < 0) { set_error("item %lld: n_nodes < 0", (long long)i); return DGFS_EINVAL; }
+    if (pl->N > 48 || pl->N % 5 == 0 || pl->N % 7 == 0) {
+      set_error("item %lld: batched launches cover N = 2^a 3^b <= 48, not N = %d (use dgfs_collide)", (long long)i, pl->N);
+      return DGFS_EUNSUPPORTED;
+    }
     if (it.n_nodes == 0) continue;
     if (!it.fp || !it.fq || !it.Q) { set_error("item %lld: NULL array", (long long)i); return DGFS_EINVAL; }
     const int64_t n3 = (int64_t)pl->N * pl->N * pl->N;

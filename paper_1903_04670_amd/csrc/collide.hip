@@ -85,6 +85,10 @@ static hipError_t launch_pipeline_T(int N, const PipeArgs &a, const FwdArgs &fw,
     case 24: return launch_pipeline_N<T, 24>(a, fw, fa, st, do_fwd, vss);
     case 32: return launch_pipeline_N<T, 32>(a, fw, fa, st, do_fwd, vss);
     case 36: return launch_pipeline_N<T, 36>(a, fw, fa, st, do_fwd, vss);
+    case 10: return launch_pipeline_N<T, 10>(a, fw, fa, st, do_fwd, vss);
+    case 14: return launch_pipeline_N<T, 14>(a, fw, fa, st, do_fwd, vss);
+    case 40: return launch_pipeline_N<T, 40>(a, fw, fa, st, do_fwd, vss);
+    case 56: return launch_pipeline_N<T, 56>(a, fw, fa, st, do_fwd, vss);
     case 48: return launch_pipeline_N<T, 48>(a, fw, fa, st, do_fwd, vss);
     default: return hipErrorInvalidValue;
   }

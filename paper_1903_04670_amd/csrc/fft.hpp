@@ -1,8 +1,8 @@
 // Register-resident 1-D complex FFTs of compile-time length for gfx950.
 //
 // One thread owns one pencil of N complex values and transforms it with a
-// fully unrolled mixed-radix decimation-in-time recursion (radix 4, 2, 3
-// codelets).  Twiddle factors are compile-time constants produced by a
+// fully unrolled mixed-radix decimation-in-time recursion (radix 4, 2, 3, 5
+// and 7 codelets).  Twiddle factors are compile-time constants produced by a
 // constexpr sine/cosine (octant reduction on the exact rational angle j/n,
 // then Taylor series on [0, pi/4]), so no table is read at run time.
 //
@@ -117,10 +117,58 @@ DGFS_HD void dft4(cplx<T>& a, cplx<T>& b, cplx<T>& c, cplx<T>& d) {
   d = csub(s1, s3);
 }
 
+// Odd-length R-point DFT (R = 5, 7) in place.  Inputs n and R - n are
+// paired: with s_n = y_n + y_{R-n} and d_n = y_n - y_{R-n},
+//   Y_k     = y_0 + sum_n s_n cos(2 pi nk/R) + DIR i sum_n d_n sin(2 pi nk/R)
+//   Y_{R-k} = the same with the sine sum's sign flipped,
+// for n, k = 1 .. (R-1)/2; the constants are compile-time.
+namespace detail {
+template <int R, int K, int NN, typename T>
+DGFS_HD void odd_terms(const cplx<T> (&s)[R], const cplx<T> (&d)[R], cplx<T> &a, cplx<T> &b) {
+  if constexpr (NN <= (R - 1) / 2) {
+    constexpr ct::SC sc = ct::sincos2pi((long long)NN * K, R);
+    constexpr T c = (T)sc.c, sn = (T)sc.s;
+    a = cplx<T>{a.x + c * s[NN].x, a.y + c * s[NN].y};
+    b = cplx<T>{b.x + sn * d[NN].x, b.y + sn * d[NN].y};
+    odd_terms<R, K, NN + 1>(s, d, a, b);
+  }
+}
+template <int R, int DIR, int K, typename T>
+DGFS_HD void odd_outputs(const cplx<T> &y0, const cplx<T> (&s)[R], const cplx<T> (&d)[R], cplx<T> (&out)[R]) {
+  if constexpr (K <= (R - 1) / 2) {
+    cplx<T> a = y0, b{(T)0, (T)0};
+    odd_terms<R, K, 1>(s, d, a, b);
+    const cplx<T> ib = mul_dir_i<DIR>(b);
+    out[K] = cadd(a, ib);
+    out[R - K] = csub(a, ib);
+    odd_outputs<R, DIR, K + 1>(y0, s, d, out);
+  }
+}
+}  // namespace detail
+
+template <int R, int DIR, typename T>
+DGFS_HD void dft_odd(cplx<T> (&y)[R]) {
+  static_assert(R % 2 == 1 && R >= 5, "odd codelet");
+  cplx<T> s[R], d[R], out[R];
+  cplx<T> sum = y[0];
+#pragma unroll
+  for (int n = 1; n <= (R - 1) / 2; ++n) {
+    s[n] = cadd(y[n], y[R - n]);
+    d[n] = csub(y[n], y[R - n]);
+    sum = cadd(sum, s[n]);
+  }
+  out[0] = sum;
+  detail::odd_outputs<R, DIR, 1>(y[0], s, d, out);
+#pragma unroll
+  for (int k = 0; k < R; ++k) y[k] = out[k];
+}
+
 template <int N> constexpr int first_radix() {
   if constexpr (N % 4 == 0) return 4;
   else if constexpr (N % 2 == 0) return 2;
   else if constexpr (N % 3 == 0) return 3;
+  else if constexpr (N % 5 == 0) return 5;
+  else if constexpr (N % 7 == 0) return 7;
   else return 0;
 }
 
@@ -135,6 +183,13 @@ struct FFTView {
       dft3<DIR>(x[OFF], x[OFF + STRIDE], x[OFF + 2 * STRIDE]);
     } else if constexpr (N == 4) {
       dft4<DIR>(x[OFF], x[OFF + STRIDE], x[OFF + 2 * STRIDE], x[OFF + 3 * STRIDE]);
+    } else if constexpr (N == 5 || N == 7) {
+      cplx<T> y[N];
+#pragma unroll
+      for (int n = 0; n < N; ++n) y[n] = x[OFF + STRIDE * n];
+      dft_odd<N, DIR>(y);
+#pragma unroll
+      for (int n = 0; n < N; ++n) x[OFF + STRIDE * n] = y[n];
     } else {
       constexpr int R = first_radix<N>();
       static_assert(R > 0, "unsupported FFT length");
@@ -162,7 +217,8 @@ struct FFTView {
       load_tw<0, k1, R, M>(x, y);
       if constexpr (R == 2) dft2<DIR>(y[0], y[1]);
       else if constexpr (R == 3) dft3<DIR>(y[0], y[1], y[2]);
-      else dft4<DIR>(y[0], y[1], y[2], y[3]);
+      else if constexpr (R == 4) dft4<DIR>(y[0], y[1], y[2], y[3]);
+      else dft_odd<R, DIR>(y);
       store_back<0, k1, R>(x, y);
       combine<k1 + 1, R, M>(x);
     }

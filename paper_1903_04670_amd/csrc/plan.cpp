@@ -115,12 +115,12 @@ extern "C" dgfs_status dgfs_sphere_set(int32_t kind, int32_t M, double *sigma, d
   return DGFS_OK;
 }
 
+// The grid sizes the kernels are instantiated for: the even N = 2^a 3^b up
+// to 48, and 10, 14, 40, 56 (radix-5 and radix-7 transforms).
 static bool supported_N(int N) {
-  if (N < 4 || N > 48 || N % 2) return false;
-  int n = N;
-  while (n % 2 == 0) n /= 2;
-  while (n % 3 == 0) n /= 3;
-  return n == 1;
+  for (int n : {4, 6, 8, 10, 12, 14, 16, 18, 24, 32, 36, 40, 48, 56})
+    if (N == n) return true;
+  return false;
 }
 
 extern "C" dgfs_status dgfs_plan_create(const dgfs_params *prm, dgfs_plan *out) {
@@ -130,7 +130,7 @@ extern "C" dgfs_status dgfs_plan_create(const dgfs_params *prm, dgfs_plan *out) 
   if (ns < 1 || ns > DGFS_MAX_SPECIES) { set_error("n_species = %d outside [1, %d]", ns, DGFS_MAX_SPECIES); return DGFS_EINVAL; }
   if (!prm->mass || !prm->omega || !prm->alpha) { set_error("mass, omega and alpha are required"); return DGFS_EINVAL; }
   if (prm->N < 2 || prm->N % 2) { set_error("N = %d must be even and >= 4", prm->N); return DGFS_EINVAL; }
-  if (!supported_N(prm->N)) { set_error("N = %d not supported (need 4 <= N <= 48, N = 2^a 3^b)", prm->N); return DGFS_EUNSUPPORTED; }
+  if (!supported_N(prm->N)) { set_error("N = %d not supported (4, 6, 8, 10, 12, 14, 16, 18, 24, 32, 36, 40, 48, 56)", prm->N); return DGFS_EUNSUPPORTED; }
   if (!(prm->L > 0.0)) { set_error("L must be > 0"); return DGFS_EINVAL; }
   if (prm->M < 1 || !prm->sigma || !prm->w_sigma) { set_error("M >= 1 with sigma and w_sigma required"); return DGFS_EINVAL; }
   if (prm->N_rho < 1) { set_error("N_rho = %d must be >= 1", prm->N_rho); return DGFS_EINVAL; }

@@ -72,6 +72,10 @@ static hipError_t launch_vjp_T(int N, const VjpArgs &v, const FwdArgs &fw, hipSt
     case 24: return launch_vjp_N<T, 24>(v, fw, st);
     case 32: return launch_vjp_N<T, 32>(v, fw, st);
     case 36: return launch_vjp_N<T, 36>(v, fw, st);
+    case 10: return launch_vjp_N<T, 10>(v, fw, st);
+    case 14: return launch_vjp_N<T, 14>(v, fw, st);
+    case 40: return launch_vjp_N<T, 40>(v, fw, st);
+    case 56: return launch_vjp_N<T, 56>(v, fw, st);
     case 48: return launch_vjp_N<T, 48>(v, fw, st);
     default: return hipErrorInvalidValue;
   }

@@ -90,3 +90,16 @@ def test_batched_uneven_instances_N16_24_32(torch_cuda, n_inst):
         seen.add(cfg["N"])
         ref = oracle_collide(oracle_pairs(cfg)[p][q], cfg["F"][0, p], cfg["F"][0, q])
         assert rel_linf(ob.cpu().numpy()[0], ref) <= 1e-11
+
+
+def test_batched_rejects_radix5_radix7_grids(torch_cuda):
+    """Batched launches cover N = 2^a 3^b <= 48; a plan on N = 40 is refused
+    before anything is launched (dgfs_collide serves it)."""
+    from paper_1903_04670_amd import dgfs
+    torch = torch_cuda
+    cfg = small_config(40, ns=1, Nrho=2, seed=90, n_nodes=1)
+    pl = gpu_plan(cfg)
+    F = torch.from_numpy(cfg["F"]).cuda()
+    out = torch.zeros(F[:, 0].shape, dtype=torch.float64, device="cuda")
+    with pytest.raises(dgfs.DGFSError, match="batched launches cover"):
+        dgfs.collide_batched([pl], [(0, 0, 0, F[:, 0], F[:, 0], out)])

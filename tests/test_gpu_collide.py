@@ -40,8 +40,8 @@ def test_homogeneous_single_species_N16(torch_cuda):
 
 
 @pytest.mark.parametrize("N,kind", [(4, "octahedron"), (6, "icosahedron"), (6, "fibonacci"), (8, "icosahedron"),
-                                    (12, "fibonacci"), (18, "octahedron"), (24, "icosahedron"),
-                                    (36, "octahedron")])
+                                    (10, "icosahedron"), (12, "fibonacci"), (14, "octahedron"),
+                                    (18, "octahedron"), (24, "icosahedron"), (36, "octahedron")])
 def test_small_sizes_all_pairs(torch_cuda, N, kind):
     cfg = small_config(N, ns=2, M_kind=kind, Nrho=3 if N < 16 else 6, seed=N, n_nodes=2)
     opl = oracle_pairs(cfg)
@@ -52,6 +52,19 @@ def test_small_sizes_all_pairs(torch_cuda, N, kind):
             for i in range(cfg["n_nodes"]):
                 ref = oracle_collide(opl[p][q], cfg["F"][i, p], cfg["F"][i, q])
                 assert rel_linf(got[i], ref) <= TOL, (N, p, q, i)
+
+
+@pytest.mark.parametrize("N,kind", [(40, "icosahedron"), (56, "octahedron")])
+def test_radix5_radix7_grids(torch_cuda, N, kind):
+    """N = 40 = 8 x 5 and N = 56 = 8 x 7 (the largest grids of the paper's
+    accuracy study), one node, a cross pair and a self pair."""
+    cfg = small_config(N, ns=2, M_kind=kind, Nrho=3, seed=N, n_nodes=1)
+    opl = oracle_pairs(cfg)
+    pl = gpu_plan(cfg)
+    for p, q in [(0, 1), (1, 1)]:
+        got = run_gpu(torch_cuda, pl, cfg["F"], p, q)
+        ref = oracle_collide(opl[p][q], cfg["F"][0, p], cfg["F"][0, q])
+        assert rel_linf(got[0], ref) <= TOL, (N, p, q)
 
 
 def test_couette_shape_N32_all_pairs(torch_cuda):

@@ -18,7 +18,8 @@ def torch_cuda():
     return torch
 
 
-@pytest.mark.parametrize("N,kind", [(8, "icosahedron"), (12, "octahedron"), (16, "fibonacci")])
+@pytest.mark.parametrize("N,kind", [(8, "icosahedron"), (10, "octahedron"), (12, "octahedron"),
+                                    (14, "icosahedron"), (16, "fibonacci")])
 def test_vjp_matches_oracle_gradient(torch_cuda, N, kind):
     from paper_1903_04670_amd import dgfs
     torch = torch_cuda

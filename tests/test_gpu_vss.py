@@ -45,7 +45,8 @@ def test_vss_gain_table_matches_oracle(torch_cuda, N, M, alpha):
                                             (16, "icosahedron", 12, 1.32), (6, "fibonacci", 5, 1.4),
                                             (8, "fibonacci", 7, 0.8), (6, "fibonacci", 5, 0.8),
                                             (6, "octahedron", 6, 1.4), (6, "icosahedron", 12, 1.4),
-                                            (12, "fibonacci", 5, 1.4), (4, "fibonacci", 5, 1.4)])
+                                            (12, "fibonacci", 5, 1.4), (4, "fibonacci", 5, 1.4),
+                                            (10, "fibonacci", 5, 1.4), (14, "octahedron", 6, 1.3)])
 def test_vss_collide_parity(torch_cuda, N, kind, M, alpha):
     from paper_1903_04670_amd import dgfs
     torch = torch_cuda
