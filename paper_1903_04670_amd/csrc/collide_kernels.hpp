@@ -374,8 +374,9 @@ __device__ __forceinline__ void gain_yz_body(const PipeArgs &a, int jx, int r, i
         acc_add(P[k].x, Pcx[k], pr.x);
         acc_add(P[k].y, Pcy[k], pr.y);
       } else {
-        P[k].x += pr.x;
-        P[k].y += pr.y;
+        // P += u1 h as two fused multiply-adds per component
+        P[k].x = __builtin_fma(u1[k].x, h[k].x, __builtin_fma(-u1[k].y, h[k].y, P[k].x));
+        P[k].y = __builtin_fma(u1[k].x, h[k].y, __builtin_fma(u1[k].y, h[k].x, P[k].y));
       }
     }
   };
@@ -551,8 +552,8 @@ __device__ __forceinline__ void gain_yz_body(const PipeArgs &a, int jx, int r, i
         }
         group_sync<N>();
       };
-#pragma unroll 1
-      for (int side = 0; side < 2; ++side) do_side(side);
+      do_side(0);
+      do_side(1);
     }
   }
   }
