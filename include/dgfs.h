@@ -149,7 +149,9 @@ dgfs_status dgfs_collide(dgfs_plan plan, int64_t n_nodes, int32_t p, int32_t q,
 /*
  * Vector-Jacobian product of dgfs_collide: for a cotangent wbar (same layout
  * as Q) returns grad_fp = (dQ/df^p)^T wbar and grad_fq = (dQ/df^q)^T wbar.
- * Intermediates of the (r, m) loop are recomputed, not stored.  When fp and
+ * Intermediates of the (r, m) loop are recomputed, not stored (VSS plans
+ * keep one transformed cotangent per (r, m) in the workspace, VHS plans one
+ * per r).  When fp and
  * fq are the same array (p == q) the gradient with respect to it is the sum
  * of the two outputs.  flags: DGFS_ACCUMULATE (add into grad_*).
  * grad_fp or grad_fq may be NULL to skip that side.

@@ -22,7 +22,7 @@ static VjpLayout vjp_layout(const dgfs_plan_s *pl, int B) {
   l.z = a256((size_t)B * 2 * n3 * c);
   l.x = a256((size_t)B * 2 * pl->Nr * pl->Sx * n3 * c);
   l.zw = a256((size_t)B * 2 * n3 * c);
-  l.vx = a256((size_t)B * pl->Nr * n3 * c);
+  l.vx = a256((size_t)B * pl->Nr * (pl->vhs ? 1 : pl->M) * n3 * c);  // VSS: one array per (r, m)
   l.y = l.x;
   l.h = a256((size_t)B * 3 * n3 * c);
   return l;
@@ -45,12 +45,18 @@ static hipError_t launch_vjp_N(const VjpArgs &v, const FwdArgs &fw, hipStream_t 
   DGFS_LAUNCH("k_inv_yz", (k_inv_yz<T, N, G>), dim3((planes_w + G - 1) / G), dim3(G * N), 0, st, v);
   DGFS_LAUNCH("k_shift_x", (k_shift_x<T, N>), dim3((N * N + 31) / 32, 2, E), dim3(64), 0, st, a);
   const int pb2 = (N * N + 31) / 32;  // lane pairs: 32 x-lines per 64-thread block
-  DGFS_LAUNCH("k_vjp_v", (k_vjp_v<T, N>), dim3(pb2, E), dim3(64), 0, st, v);
   constexpr int GV = 128 / (2 * N) > 0 ? 128 / (2 * N) : 1;  // groups per block, as the plan's VJP schedule
-  if (a.pack)
-    DGFS_LAUNCH("k_vjp_yz", (k_vjp_yz<T, N, GV, false>), dim3(N, a.Nr, E), dim3(GV * 2 * N), 0, st, v);
-  else
-    DGFS_LAUNCH("k_vjp_yz", (k_vjp_yz<T, N, GV>), dim3(N, a.Nr, E), dim3(GV * 2 * N), 0, st, v);
+  const dim3 gyz(N, a.Nr, E), byz(GV * 2 * N);
+  // the scalar-phase path needs unzeroed twiddle rows (no nyquist_zero)
+  if (v.vss) {
+    DGFS_LAUNCH("k_vjp_v", (k_vjp_v<T, N, true>), dim3(pb2, E), dim3(64), 0, st, v);
+    if (v.nyq) DGFS_LAUNCH("k_vjp_yz", (k_vjp_yz<T, N, GV, false, true>), gyz, byz, 0, st, v);
+    else DGFS_LAUNCH("k_vjp_yz", (k_vjp_yz<T, N, GV, true, true>), gyz, byz, 0, st, v);
+  } else {
+    DGFS_LAUNCH("k_vjp_v", (k_vjp_v<T, N>), dim3(pb2, E), dim3(64), 0, st, v);
+    if (v.nyq) DGFS_LAUNCH("k_vjp_yz", (k_vjp_yz<T, N, GV, false>), gyz, byz, 0, st, v);
+    else DGFS_LAUNCH("k_vjp_yz", (k_vjp_yz<T, N, GV>), gyz, byz, 0, st, v);
+  }
   if (v.sym)
     DGFS_LAUNCH("k_vjp_x", (k_vjp_x<T, N, true>), dim3(pb2, E), dim3(64), 0, st, v);
   else
@@ -93,7 +99,6 @@ extern "C" dgfs_status dgfs_collide_vjp(dgfs_plan pl, int64_t n_nodes, int32_t p
   if (n_nodes < 0) { set_error("dgfs_collide_vjp: n_nodes < 0"); return DGFS_EINVAL; }
   if (p < 0 || q < 0 || p >= pl->ns || q >= pl->ns) { set_error("dgfs_collide_vjp: species out of range"); return DGFS_EINVAL; }
   if (flags & ~DGFS_ACCUMULATE) { set_error("dgfs_collide_vjp: unsupported flags 0x%x", flags); return DGFS_EINVAL; }
-  if (!pl->vhs) { set_error("dgfs_collide_vjp: only VHS plans (alpha = 1) have an adjoint in this build"); return DGFS_EUNSUPPORTED; }
   if (n_nodes == 0) return DGFS_OK;
   if (!fp || !fq || !wbar || (!grad_fp && !grad_fq)) { set_error("dgfs_collide_vjp: NULL array"); return DGFS_EINVAL; }
   const int64_t n3 = (int64_t)pl->N * pl->N * pl->N;
@@ -126,7 +131,10 @@ extern "C" dgfs_status dgfs_collide_vjp(dgfs_plan pl, int64_t n_nodes, int32_t p
   const bool same = p == q && fp == fq;
   v.a.xshare[0] = same ? 1 : 0;
   pipeline_slots(pl, v.a);
-  v.sym = (same && pl->antipodal) ? 1 : 0;
+  // the symmetric shortcut needs a direction-independent table (VHS)
+  v.sym = (same && pl->antipodal && pl->vhs) ? 1 : 0;
+  v.vss = pl->vhs ? 0 : 1;
+  v.nyq = pl->nyquist_zero ? 1 : 0;
   v.f_stride = node_stride;
   v.w_stride = wbar_stride;
   v.g_stride = grad_stride;

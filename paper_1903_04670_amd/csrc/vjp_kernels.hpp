@@ -5,11 +5,13 @@
 //   grad_g = beta Re F( sum_rm P2_rm * iF(u1_rm * F(W * u)) ) - beta Re F(c * iF(f * wbar))
 // P1 = e^{+i th_q sigma.l}, P2 = e^{-i th_p sigma.l}; u1 = iF(P1 F f), u2 = iF(P2 F g)
 // are recomputed per (r, m) from the same X arrays as the forward pipeline.
-// For VHS, F(W * u) = w_m v_r with v_r = F(w_r b_r * u).
+// For VHS, F(W * u) = w_m v_r with v_r = F(w_r b_r * u); for VSS the table
+// depends on the direction and v_rm = F(w_r w_m b_rm * u) is formed per term.
 //
 // Stages (arrays N^3 complex, [x][y][z]):
 //   Zw   = iFFT_yz(wbar), Zfw = iFFT_yz(f * wbar)                         k_inv_yz
 //   X1, X2 (as the forward), Vx_r = FFT_x(g_r(|k|) iFFT_x Zw)              k_shift_x, k_vjp_v
+//     (VSS: Vx_rm = FFT_x(b_rm(k) iFFT_x Zw), b_rm carrying w_r w_m / N^3)
 //   Y1_rs = sum_{m: s(m)=s} P1yz_rm iFFT_yz(w_m u2_rm v_r)  (plane jx)     k_vjp_yz
 //   Y2_rs = sum_{m: s(m)=s} P2yz_rm iFFT_yz(w_m u1_rm v_r)
 //   Hf = FFT_x(sum_rs P1x_rs iFFT_x Y1_rs / N^3)                           k_vjp_x
@@ -35,6 +37,8 @@ struct VjpArgs {
   const int *sched;     // [G][sched_T] term schedule of k_vjp_yz (m | side << 16 | last << 17, or -1)
   int sched_T;
   int sym;              // 1: the two sides' gain sums coincide; only side 0's Y is formed
+  int vss;              // 1: direction-dependent table, Vx is [e][Nr][M][N^3]
+  int nyq;              // 1: the plan's twiddle rows have zeroed Nyquist entries
 };
 
 // iFFT_yz of wbar and of f*wbar on plane jx of each node (rows first through
@@ -74,11 +78,11 @@ __global__ void __launch_bounds__(G * N) k_inv_yz(VjpArgs v) {
   }
 }
 
-// Vx_r = FFT_x(g_r(|k|) iFFT_x Zw) for every r.  Lane pair (pencil, p) =
-// x-line (y, z): iFFT_x of the decimated half x = 2n + p gives wave numbers
-// pH + k; after the table multiply a decimation-in-frequency FFT_x returns
-// to x = 2k + p.
-template <typename T, int N>
+// Vx_r = FFT_x(g_r(|k|) iFFT_x Zw) for every r (VSS: Vx_rm with the complex
+// table b_rm(k) for every (r, m)).  Lane pair (pencil, p) = x-line (y, z):
+// iFFT_x of the decimated half x = 2n + p gives wave numbers pH + k; after
+// the table multiply a decimation-in-frequency FFT_x returns to x = 2k + p.
+template <typename T, int N, bool VSS = false>
 __global__ void __launch_bounds__(64) k_vjp_v(VjpArgs v) {
   constexpr int H = N / 2;
   const PipeArgs &a = v.a;
@@ -96,6 +100,22 @@ __global__ void __launch_bounds__(64) k_vjp_v(VjpArgs v) {
 #pragma unroll
   for (int n = 0; n < H; ++n) U[n] = Zw[(size_t)(2 * n + p) * N * N + pc];
   fft_pair<N, +1>(U, p);
+  if constexpr (VSS) {
+    const C<T> *B = static_cast<const C<T> *>(pd.btab);  // [Nr][M][N^3], natural wave order
+    C<T> *Vx = static_cast<C<T> *>(v.Vx) + (size_t)e * a.Nr * a.M * n3;
+    for (int rm = 0; rm < a.Nr * a.M; ++rm) {
+      const C<T> *bl = B + (size_t)rm * n3;
+      C<T> w[H];
+#pragma unroll
+      for (int k = 0; k < H; ++k) w[k] = cmul(U[k], bl[(size_t)(p * H + k) * N * N + pc]);
+      fft_pair_dif<N, -1>(w, p);
+      if (valid) {
+#pragma unroll
+        for (int k = 0; k < H; ++k) Vx[(size_t)rm * n3 + (size_t)(2 * k + p) * N * N + pc] = w[k];
+      }
+    }
+    return;
+  }
   const T *gt = static_cast<const T *>(pd.gtab);
   C<T> *Vx = static_cast<C<T> *>(v.Vx) + (size_t)e * a.Nr * n3;
   for (int r = 0; r < a.Nr; ++r) {
@@ -124,7 +144,9 @@ __global__ void __launch_bounds__(64) k_vjp_v(VjpArgs v) {
 // side) unit writes Y_side[r][s] for the plane.
 // SCALAR = false for plans whose twiddle tables have zeroed Nyquist entries
 // (the scalar-phase identities of the N = 32 path do not hold for them).
-template <typename T, int N, int G, bool SCALAR = true>
+// VSS: each term forms its own v_rm on the plane (two more passes through
+// the group's LDS plane), and w_m is already in the table.
+template <typename T, int N, int G, bool SCALAR = true, bool VSS = false>
 __global__ void __launch_bounds__(G * 2 * N) k_vjp_yz(VjpArgs v) {
   constexpr int H = N / 2;
   const PipeArgs &a = v.a;
@@ -140,10 +162,11 @@ __global__ void __launch_bounds__(G * 2 * N) k_vjp_yz(VjpArgs v) {
   C<T>(*buf)[N + 1] = lds[g < G ? g : 0];
   const bool in_group = g < G;
   C<T> vr[H];
-  {
-    const C<T> *src = static_cast<const C<T> *>(v.Vx) + ((size_t)e * a.Nr + r) * n3 + (size_t)jx * N * N;
+  // v = FFT_yz of the Vx array `arr` on this plane: row y = c, z = pH + k
+  auto form_v = [&](bool on, size_t arr) {
+    const C<T> *src = static_cast<const C<T> *>(v.Vx) + arr * n3 + (size_t)jx * N * N;
     C<T> h[H];
-    if (in_group) {
+    if (on) {
 #pragma unroll
       for (int n = 0; n < H; ++n) h[n] = src[(2 * n + p) * N + c];
       fft_pair<N, -1>(h, p);
@@ -151,7 +174,7 @@ __global__ void __launch_bounds__(G * 2 * N) k_vjp_yz(VjpArgs v) {
       for (int k = 0; k < H; ++k) buf[p * H + k][c] = h[k];
     }
     group_sync<N>();
-    if (in_group) {
+    if (on) {
 #pragma unroll
       for (int n = 0; n < H; ++n) h[n] = buf[c][2 * n + p];
       fft_pair<N, -1>(h, p);
@@ -159,7 +182,8 @@ __global__ void __launch_bounds__(G * 2 * N) k_vjp_yz(VjpArgs v) {
       for (int k = 0; k < H; ++k) vr[k] = h[k];
     }
     group_sync<N>();
-  }
+  };
+  if constexpr (!VSS) form_v(in_group, (size_t)e * a.Nr + r);
   const C<T> *X = static_cast<const C<T> *>(a.X) + (size_t)e * 2 * a.Nr * a.Sx * n3;
   C<T> *Y = static_cast<C<T> *>(v.Y) + (size_t)e * 2 * a.Nr * a.Sx * n3;
   C<T> acc[H];
@@ -172,6 +196,7 @@ __global__ void __launch_bounds__(G * 2 * N) k_vjp_yz(VjpArgs v) {
     const int m = active ? (ent & 0xffff) : 0;
     const int side = (ent >> 16) & 1, uside = 1 - side;
     const int s = a.sidx[m];
+    if constexpr (VSS) form_v(active, ((size_t)e * a.Nr + r) * a.M + m);
     if (active) {
       const C<T> *src = x_plane(a, X, slot, uside, r, s, n3) + (size_t)jx * N * N;
       C<T> h[H];
@@ -188,7 +213,7 @@ __global__ void __launch_bounds__(G * 2 * N) k_vjp_yz(VjpArgs v) {
 #pragma unroll
       for (int n = 0; n < H; ++n) h[n] = buf[c][2 * n + p];
       fft_pair<N, +1>(h, p);  // u on row y = c, z = pH + k
-      const T w = uload(wm, m);
+      const T w = VSS ? (T)1 : uload(wm, m);
 #pragma unroll
       for (int k = 0; k < H; ++k) h[k] = cscale(cmul(h[k], vr[k]), w);
       fft_pair_dif<N, +1>(h, p);  // iFFT_z of the product: z = 2k + p

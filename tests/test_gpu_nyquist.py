@@ -130,6 +130,27 @@ def test_vjp_of_the_variant(torch_cuda, N, kind):
         assert rel_linf(gq[0].cpu().numpy(), rq) <= TOL, (N, p, q)
 
 
+def test_vss_vjp_of_the_variant_N32(torch_cuda):
+    """A VSS plan with the option at N = 32: the adjoint's column phases take
+    the per-lane path (zeroed twiddle rows) and each (r, m) term forms its
+    own v_rm."""
+    from paper_1903_04670_amd import dgfs
+    torch = torch_cuda
+    cfg = small_config(32, ns=2, M_kind="fibonacci", Nrho=2, seed=5, n_nodes=1)
+    cfg["alpha"] = np.full((2, 2), 1.3)
+    W = np.random.default_rng(1).standard_normal((1, 32, 32, 32))
+    opl = oracle_pairs(cfg, nyquist_zero=True)
+    pl = gpu_plan(cfg, nyquist_zero=True)
+    F = torch.from_numpy(cfg["F"]).cuda()
+    Wd = torch.from_numpy(W).cuda()
+    for p, q in [(0, 1), (1, 1)]:
+        gf, gq = dgfs.collide_vjp(pl, p, q, F[:, p], F[:, q], Wd)
+        torch.cuda.synchronize()
+        rf, rq = oracle_vjp(opl[p][q], cfg["F"][0, p], cfg["F"][0, q], W[0])
+        assert rel_linf(gf[0].cpu().numpy(), rf) <= TOL, (p, q)
+        assert rel_linf(gq[0].cpu().numpy(), rq) <= TOL, (p, q)
+
+
 def test_vss_plan_with_the_variant(torch_cuda):
     """A VSS plan (alpha != 1) honours the option through its zeroed twiddle
     tables (its gain kernel is not packed)."""

@@ -39,6 +39,31 @@ def test_vjp_matches_oracle_gradient(torch_cuda, N, kind):
             assert rel_linf(gq[i].cpu().numpy(), rq) <= 1e-11, (p, q, i)
 
 
+@pytest.mark.parametrize("N,kind,alpha", [(8, "fibonacci", 1.4), (10, "icosahedron", 1.2),
+                                          (12, "octahedron", 1.3), (16, "fibonacci", 0.8)])
+def test_vss_vjp_matches_oracle_gradient(torch_cuda, N, kind, alpha):
+    """VSS plans (alpha != 1): the direction-dependent table gives one
+    v_rm = F(w_r w_m b_rm u) per (r, m) term; against the oracle's gradient
+    (its transposition holds for any table) at 1e-11."""
+    from paper_1903_04670_amd import dgfs
+    torch = torch_cuda
+    cfg = small_config(N, ns=2, M_kind=kind, Nrho=3, seed=30 + N, n_nodes=2)
+    cfg["alpha"] = np.full((2, 2), alpha)
+    rng = np.random.default_rng(N + 1)
+    W = rng.standard_normal((2, N, N, N))
+    opl = oracle_pairs(cfg)
+    pl = gpu_plan(cfg)
+    F = torch.from_numpy(cfg["F"]).cuda()
+    Wd = torch.from_numpy(W).cuda()
+    for p, q in [(0, 1), (1, 0), (1, 1)]:
+        gf, gq = dgfs.collide_vjp(pl, p, q, F[:, p], F[:, q], Wd)
+        torch.cuda.synchronize()
+        for i in range(2):
+            rf, rq = oracle_vjp(opl[p][q], cfg["F"][i, p], cfg["F"][i, q], W[i])
+            assert rel_linf(gf[i].cpu().numpy(), rf) <= 1e-11, (N, p, q, i)
+            assert rel_linf(gq[i].cpu().numpy(), rq) <= 1e-11, (N, p, q, i)
+
+
 @pytest.mark.parametrize("n_nodes,n_dirs", [(4, 16), (256, 64)])
 def test_vjp_central_differences_N32(torch_cuda, n_nodes, n_dirs):
     """Two species (masses 1, 2.5), N = 32, icosahedron, N_rho = 16, on 4
