@@ -53,10 +53,10 @@ static hipError_t launch_pipeline_N(const PipeArgs &a, const FwdArgs &fw, const 
       default: DGFS_LAUNCH("k_shift_x", (k_shift_x<T, N, 2>), dim3(pb2, 4, EG), dim3(64), 0, st, a); break;
     }
   }
-  constexpr int GG = gain_groups<N>();
+  constexpr int GG = gain_groups<N>(), GP = packed_gain_groups<N>();
   if (!vss) {
     if (a.pack)
-      DGFS_LAUNCH("k_gain_yz", (k_gain_yz<T, N, GG, 1, true>), dim3(N, a.Nr, EG), dim3(GG * 2 * N), 0, st, a);
+      DGFS_LAUNCH("k_gain_yz", (k_gain_yz<T, N, GP, 1, true>), dim3(N, a.Nr, EG), dim3(GP * 2 * N), 0, st, a);
     else
       DGFS_LAUNCH("k_gain_yz", (k_gain_yz<T, N, GG>), dim3(N, a.Nr, EG), dim3(GG * 2 * N), 0, st, a);
     DGFS_LAUNCH("k_gain_x", (k_gain_x<T, N, sizeof(T) == 4>), dim3(pb2, sizeof(T) == 4 ? EG : E), dim3(64), 0, st, a);

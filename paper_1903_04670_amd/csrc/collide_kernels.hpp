@@ -301,6 +301,14 @@ __global__ void __launch_bounds__(64) k_shift_x(PipeArgs a) {
 // occupancy below what its registers allow.
 template <typename T> constexpr int gain_bufs() { return sizeof(T) == 4 ? 2 : 1; }
 
+// Groups per block of the real-packed gain path: one wave at N = 32 (the
+// block's final transform then idles no second group), else as the literal
+// path.  The batched kernel uses the same count, so results match bit for
+// bit.
+template <int N> constexpr int packed_gain_groups() {
+  return N == 32 ? 1 : (128 / (2 * N) > 0 ? 128 / (2 * N) : 1);
+}
+
 // LDS of k_gain_yz besides its planes: per group the yz phase rows of its
 // current direction, [2 sides][2N] (y phases, then z phases).
 template <typename T, int N, int G> constexpr size_t gain_phase_elems() { return (size_t)G * 4 * N; }
