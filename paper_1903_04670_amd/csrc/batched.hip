@@ -99,7 +99,7 @@ __global__ void __launch_bounds__(128) kb_gain_yz(const SubItem *items, const in
     auto *phs = reinterpret_cast<C<T> *>(smem + (size_t)g_gain<NN>() * gain_bufs<T>() * NN * (NN + 1) * sizeof(C<T>));
     if (si.vss) gain_yz_vss_body<T, NN, g_gain<NN>()>(si.a, jx, r, e, threadIdx.x, lds, phs);
     else if (si.a.pack) gain_yz_body<T, NN, packed_gain_groups<NN>(), 1, true>(si.a, jx, r, e, threadIdx.x, lds, phs);
-    else gain_yz_body<T, NN, g_gain<NN>()>(si.a, jx, r, e, threadIdx.x, lds, phs);
+    else gain_yz_body<T, NN, literal_gain_groups<T, NN>()>(si.a, jx, r, e, threadIdx.x, lds, phs);
   });
 }
 

@@ -53,7 +53,7 @@ static hipError_t launch_pipeline_N(const PipeArgs &a, const FwdArgs &fw, const 
       default: DGFS_LAUNCH("k_shift_x", (k_shift_x<T, N, 2>), dim3(pb2, 4, EG), dim3(64), 0, st, a); break;
     }
   }
-  constexpr int GG = gain_groups<N>(), GP = packed_gain_groups<N>();
+  constexpr int GG = literal_gain_groups<T, N>(), GP = packed_gain_groups<N>();
   if (!vss) {
     if (a.pack)
       DGFS_LAUNCH("k_gain_yz", (k_gain_yz<T, N, GP, 1, true>), dim3(N, a.Nr, EG), dim3(GP * 2 * N), 0, st, a);
@@ -63,7 +63,8 @@ static hipError_t launch_pipeline_N(const PipeArgs &a, const FwdArgs &fw, const 
   } else {
     constexpr int TE = N >= 48 ? 1 : 2;
     const int egroups = a.n_pairs * ((a.n_nodes + TE - 1) / TE);
-    DGFS_LAUNCH("k_gain_yz_vss", (k_gain_yz_vss<T, N, GG>), dim3(N, a.Nr, EG), dim3(GG * 2 * N), 0, st, a);
+    constexpr int GV = gain_groups<N>();
+    DGFS_LAUNCH("k_gain_yz_vss", (k_gain_yz_vss<T, N, GV>), dim3(N, a.Nr, EG), dim3(GV * 2 * N), 0, st, a);
     DGFS_LAUNCH("k_gain_x_vss", (k_gain_x_vss<T, N, TE>), dim3(pb2, egroups), dim3(64), 0, st, a);
   }
   const int fplanes = N * a.n_nodes * fa.n_out;

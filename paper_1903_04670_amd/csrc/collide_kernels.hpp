@@ -301,12 +301,16 @@ __global__ void __launch_bounds__(64) k_shift_x(PipeArgs a) {
 // occupancy below what its registers allow.
 template <typename T> constexpr int gain_bufs() { return sizeof(T) == 4 ? 2 : 1; }
 
-// Groups per block of the real-packed gain path: one wave at N = 32 (the
-// block's final transform then idles no second group), else as the literal
-// path.  The batched kernel uses the same count, so results match bit for
-// bit.
-template <int N> constexpr int packed_gain_groups() {
-  return N == 32 ? 1 : (128 / (2 * N) > 0 ? 128 / (2 * N) : 1);
+// Groups per k_gain_yz block: at least 128 threads, except one wave per
+// block for the real-packed path at N = 32 and for the FP32 two-plane
+// kernel at N = 32 (measured faster: the block's final transform then idles
+// no second group).  The FP64 literal kernel keeps two (measured faster).
+// The batched kernel uses the same counts, so results match bit for bit,
+// and the plan builds the FP32 N = 32 term schedule for one group.
+template <int N> constexpr int default_gain_groups() { return 128 / (2 * N) > 0 ? 128 / (2 * N) : 1; }
+template <int N> constexpr int packed_gain_groups() { return N == 32 ? 1 : default_gain_groups<N>(); }
+template <typename T, int N> constexpr int literal_gain_groups() {
+  return (sizeof(T) == 4 && N == 32) ? 1 : default_gain_groups<N>();
 }
 
 // LDS of k_gain_yz besides its planes: per group the yz phase rows of its

@@ -332,7 +332,9 @@ extern "C" dgfs_status dgfs_plan_create(const dgfs_params *prm, dgfs_plan *out) 
   // least loaded group); an entry is m | first << 16 (first: the column
   // passes run before this term), padded with -1 to a common length T.
   auto gain_sched = [&](const std::vector<int> &dirs, std::vector<int> &table) {
-    const int G = std::max(1, 128 / (2 * N));
+    // the schedule serves the FP32 two-plane gain kernel at N = 32, which
+    // runs one group per block (literal_gain_groups)
+    const int G = N == 32 ? 1 : std::max(1, 128 / (2 * N));
     std::vector<std::vector<int>> classes;
     for (int m : dirs) {
       int found = -1;
