@@ -69,6 +69,29 @@ def test_packed_gain_couette_N32_all_pairs(torch_cuda):
             assert err <= TOL, (p, q)
 
 
+def test_packed_gain_couette_full_size_rhs_sampled_nodes(torch_cuda):
+    """The benchmark's workload at full size (64 nodes, two species, N = 32,
+    M = 12, N_rho = 16) with the option, as the benchmark's variant line
+    times it (two launches of 32 nodes, half-spectrum x-shifted arrays, one
+    wave per gain block): against the oracle's variant at the first and the
+    last node, each bit-identical to a call on that node alone."""
+    from paper_1903_04670_amd import dgfs
+    torch = torch_cuda
+    cfg = wl.couette_two_species()
+    pl = gpu_plan(cfg, nyquist_zero=True)
+    F = torch.from_numpy(cfg["F"]).cuda()
+    got = dgfs.rhs(pl, F).cpu().numpy()
+    opl = oracle_pairs(cfg, nyquist_zero=True)
+    for i in (0, cfg["n_nodes"] - 1):
+        ref = mixture_collision(opl, cfg["F"][i:i + 1])[0]
+        err = rel_linf(got[i], ref)
+        print("nyquist-zero full-size rhs node %d: rel Linf %.3e" % (i, err))
+        assert err <= TOL, i
+        alone = dgfs.rhs(pl, F[i:i + 1].contiguous()).cpu().numpy()[0]
+        assert np.array_equal(alone, got[i]), i
+    assert np.isfinite(got).all()
+
+
 @pytest.mark.parametrize("sphere", ["icosahedron", "octahedron"])
 def test_packed_gain_symmetric_schedule_three_species(torch_cuda, sphere, monkeypatch):
     """Mixture collision term of three species through dgfs_rhs (mirrored
