@@ -77,8 +77,7 @@ typedef enum { DGFS_OP_COLLIDE = 0, DGFS_OP_VJP = 1, DGFS_OP_RHS = 2, DGFS_OP_ST
  *                  number, beta = mu^{1/2-omega} alpha/(2^{1+alpha}
  *                  Gamma(5/2-omega) pi), mu = m_p m_q/(m_p+m_q)
  *   N              velocity points per axis: 4, 6, 8, 10, 12, 14, 16, 18, 24,
- *                  32, 36, 40, 48 or 56 (dgfs_collide_batched: N <= 48 and
- *                  N = 2^a 3^b)
+ *                  32, 36, 40, 48 or 56
  *   L              velocity box half-width: D_L = [-L, L]^3
  *   S              support radius of f (informational; R defaults from L)
  *   R[ns*ns]       truncation radius of the relative-velocity ball; NULL =>

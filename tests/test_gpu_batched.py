@@ -92,14 +92,21 @@ def test_batched_uneven_instances_N16_24_32(torch_cuda, n_inst):
         assert rel_linf(ob.cpu().numpy()[0], ref) <= 1e-11
 
 
-def test_batched_rejects_radix5_radix7_grids(torch_cuda):
-    """Batched launches cover N = 2^a 3^b <= 48; a plan on N = 40 is refused
-    before anything is launched (dgfs_collide serves it)."""
-    from paper_1903_04670_amd import dgfs
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_batched_radix5_radix7_grids_equal_single_calls(torch_cuda, precision):
+    """Items on N = 10, 14, 40, 56 (radix-5 and radix-7 transforms) with an
+    N = 16 item in one batched launch per stage (the N <= 56 class): bit for
+    bit the single-plan results; the N = 40 item against the oracle."""
     torch = torch_cuda
-    cfg = small_config(40, ns=1, Nrho=2, seed=90, n_nodes=1)
-    pl = gpu_plan(cfg)
-    F = torch.from_numpy(cfg["F"]).cuda()
-    out = torch.zeros(F[:, 0].shape, dtype=torch.float64, device="cuda")
-    with pytest.raises(dgfs.DGFSError, match="batched launches cover"):
-        dgfs.collide_batched([pl], [(0, 0, 0, F[:, 0], F[:, 0], out)])
+    insts = []
+    for k, (N, ns) in enumerate([(10, 2), (14, 1), (16, 2), (40, 1), (56, 1)]):
+        insts.append(small_config(N, ns=ns, Nrho=2, seed=90 + k, n_nodes=1,
+                                  M_kind="octahedron" if N >= 40 else "icosahedron"))
+    plans, items, outs_b, outs_s = _run(torch, insts, precision)
+    for ob, os_ in zip(outs_b, outs_s):
+        assert torch.equal(ob, os_)
+    if precision == "fp64":
+        cfg = insts[3]
+        ref = oracle_collide(oracle_pairs(cfg)[0][0], cfg["F"][0, 0], cfg["F"][0, 0])
+        got = [ob for (k, p, q, _, _, ob) in items if k == 3][0].cpu().numpy()[0]
+        assert rel_linf(got, ref) <= 1e-11
