@@ -111,7 +111,9 @@ __global__ void __launch_bounds__(64) kb_gain_x(const SubItem *items, const int 
     constexpr int NN = decltype(nn)::value;
     const int pb = (NN * NN + 31) / 32;
     if (si.vss) gain_x_vss_body<T, NN, te_vss<NN>()>(si.a, local % pb, local / pb, threadIdx.x);
-    else gain_x_body<T, NN>(si.a, local % pb, local / pb, threadIdx.x);
+    // the single-plan FP32 kernel's body (its mirrored-slot pass is idle for
+    // a one-pair item), so that both compile to the same arithmetic
+    else gain_x_body<T, NN, sizeof(T) == 4>(si.a, local % pb, local / pb, threadIdx.x);
   });
 }
 
