@@ -34,7 +34,7 @@ def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--workload", default="couette", choices=["couette", "vjp", "batched", "vss"],
@@ -92,7 +92,14 @@ TRAFFIC_PROFILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "prof
 KERNEL_SOURCES = ["collide_kernels.hpp", "fft.hpp", "collide.hip"]
 
 
-def measured_traffic(kernel):
+def measured_path_bytes():
+    """rocprofv3-measured HBM bytes per FP64 evaluation of the whole path
+    (every kernel of a step) from the committed summary, or None when the
+    kernel sources changed since the counters were taken."""
+    return measured_traffic("fp64", key_prefix="path_bytes_per_eval ")
+
+
+def measured_traffic(kernel, key_prefix="traffic_bytes "):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 --pmc
     summary (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None when the
     kernel sources changed since the counters were taken."""
@@ -110,9 +117,9 @@ def measured_traffic(kernel):
     for line in text.splitlines():
         if line.startswith("source_sha256:"):
             vals["sha"] = line.split(":", 1)[1].strip()
-        elif line.startswith("traffic_bytes "):
-            k, v = line[len("traffic_bytes "):].rsplit(":", 1)
-            vals[k.strip()] = float(v)
+        elif line.startswith(key_prefix):
+            k, v = line.rsplit(":", 1)
+            vals[k[len(key_prefix):].strip()] = float(v)
     if vals.get("sha") != h.hexdigest():
         return None
     for k, v in vals.items():
@@ -426,7 +433,10 @@ def main():
                                / (HBM_PEAK_GBS * 1e9), 4),
             "fp32_mixed_frac": round(evals_per_step / (r32["ms"] / 1e3)
                                      * model_bytes_per_eval(cfg["N"], cfg["M"], cfg["Nrho"], 4)
-                                     / (HBM_PEAK_GBS * 1e9), 4)},
+                                     / (HBM_PEAK_GBS * 1e9), 4),
+            "measured_bytes_per_eval_fp64": measured_path_bytes(),
+            "measured_path_GBps_fp64": (None if measured_path_bytes() is None
+                                        else round(value * measured_path_bytes() / 1e9, 1))},
         "nyquist_zero": {
             "what": "variant operator, not the headline: the gain's translates drop the Nyquist planes of "
                     "fft(f), so u1, u2 are real and one complex transform gives both (real-packed k_gain_yz)",
