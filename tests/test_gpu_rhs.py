@@ -99,8 +99,9 @@ def test_couette_full_size_rhs_sampled_nodes(torch_cuda):
     """The benchmark's workload at full size (64 nodes, two species, N = 32,
     M = 12, N_rho = 16) in the launch configuration the benchmark times: the
     collision part of dgfs_rhs over all nodes (several launches, mirrored and
-    half-set gain slots) against the oracle at the first and the last node,
-    and each sampled node bit-identical to a call on that node alone."""
+    half-set gain slots) against the oracle at four nodes across both
+    launches (all four ordered pairs each), and each sampled node
+    bit-identical to a call on that node alone."""
     from paper_1903_04670_amd import dgfs
     torch = torch_cuda
     cfg = wl.couette_two_species()
@@ -108,7 +109,7 @@ def test_couette_full_size_rhs_sampled_nodes(torch_cuda):
     F = torch.from_numpy(cfg["F"]).cuda()
     got = dgfs.rhs(pl, F).cpu().numpy()
     opl = oracle_pairs(cfg)
-    for i in (0, cfg["n_nodes"] - 1):
+    for i in (0, 21, 42, cfg["n_nodes"] - 1):
         ref = mixture_collision(opl, cfg["F"][i:i + 1])[0]
         assert rel_linf(got[i], ref) <= TOL, i
         alone = dgfs.rhs(pl, F[i:i + 1].contiguous()).cpu().numpy()[0]
