@@ -45,7 +45,7 @@ typedef struct dgfs_plan_s *dgfs_plan;
 typedef enum {
   DGFS_OK = 0,
   DGFS_EINVAL = -1,       /* invalid argument */
-  DGFS_EUNSUPPORTED = -2, /* valid but not supported (e.g. an N with a prime factor > 3) */
+  DGFS_EUNSUPPORTED = -2, /* valid but not supported (e.g. an N the kernels are not built for) */
   DGFS_ENOMEM = -3,       /* plan tables could not be allocated */
   DGFS_EHIP = -4,         /* a HIP runtime call or launch failed */
   DGFS_EWORKSPACE = -5,   /* ws NULL or ws_bytes too small */

@@ -67,7 +67,8 @@ def _params(**over):
     (dict(N_rho=0), -1), (dict(n_species=0), -1), (dict(n_species=5), -1),
     (dict(mass=[-1.0]), -1), (dict(alpha=[0.0]), -1), (dict(omega=[3.0]), -1),
     (dict(L=0.0), -1), (dict(precision=7), -1), (dict(dg_order=-1), -1),
-    (dict(sigma=[2.0, 0, 0] * 12), -1),
+    (dict(sigma=[2.0, 0, 0] * 12), -1), (dict(nyquist_zero=2), -1), (dict(N=22), -2),
+    (dict(N=28), -2),
 ])
 def test_plan_create_validation(over, status):
     from paper_1903_04670_amd import dgfs
