@@ -27,8 +27,8 @@ def _couette_small(N=8, K=3, P=2, seed=7, ns=2):
     return cfg
 
 
-def _oracle_rhs(cfg, F, project=False):
-    opl = oracle_pairs(cfg)
+def _oracle_rhs(cfg, F, project=False, nyquist_zero=False):
+    opl = oracle_pairs(cfg, nyquist_zero=nyquist_zero)
     prob = odg.Couette1D(cfg["N"], cfg["L"], cfg["masses"], cfg["K"], cfg["P"], cfg["u_left"], cfg["u_right"])
 
     def coll(X):
@@ -159,6 +159,27 @@ def test_ssp_rk3_steps_with_graph_replay(torch_cuda):
     dgfs.step(pl, G, dt, 3, mesh=mesh, project=True, ws=ws)
     torch.cuda.synchronize()
     assert torch.equal(F, G)
+
+
+def test_ssp_rk3_graph_steps_with_the_nyquist_zero_option(torch_cuda):
+    """The same graph-replayed SSP-RK3 steps for a plan with the
+    Nyquist-zeroed gain (real-packed kernels, half-spectrum x-shifted
+    arrays inside the captured graph), against the oracle's variant."""
+    from paper_1903_04670_amd import dgfs
+    torch = torch_cuda
+    cfg = _couette_small(seed=12)
+    prob, coll = _oracle_rhs(cfg, cfg["F"], project=True, nyquist_zero=True)
+    pl = gpu_plan(cfg, dg_order=cfg["P"], nyquist_zero=True)
+    mesh = dgfs.make_mesh(cfg["K"])
+    F = torch.from_numpy(cfg["F"]).cuda()
+    ws = dgfs.workspace(pl, F.shape[0], dgfs.OP_STEP)
+    ref = cfg["F"].copy()
+    dt = 2e-3
+    for k in range(3):
+        dgfs.step(pl, F, dt, 1, mesh=mesh, project=True, ws=ws)
+        torch.cuda.synchronize()
+        ref = odg.ssp_rk3(ref, dt, lambda X: prob.rhs(X, coll))
+        assert rel_linf(F.cpu().numpy(), ref) <= 1e-12, k
 
 
 def test_argument_errors_are_reported(torch_cuda):

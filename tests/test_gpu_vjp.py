@@ -64,6 +64,32 @@ def test_vss_vjp_matches_oracle_gradient(torch_cuda, N, kind, alpha):
             assert rel_linf(gq[i].cpu().numpy(), rq) <= 1e-11, (N, p, q, i)
 
 
+def test_fp32_mixed_vjp_error_bound(torch_cuda):
+    """An FP32-mixed plan's adjoint (FP32 transforms, FP64 inputs and
+    outputs) against the FP64 oracle's gradient on the two-species N = 32
+    node, within 1e-5 of the gradient's largest entry.  With a random
+    cotangent there is none of the forward operator's gain/loss
+    cancellation, so the error is that of the FP32 transform chain: about
+    five 3-D transforms of 3 log2(32) = 15 rounding stages each, 75 x 6e-8
+    = 4.5e-6."""
+    from paper_1903_04670_amd import dgfs
+    torch = torch_cuda
+    cfg = wl.couette_two_species(K=1, P=0)
+    N = cfg["N"]
+    W = np.random.default_rng(7).standard_normal((1, N, N, N))
+    opl = oracle_pairs(cfg)
+    pl = gpu_plan(cfg, precision="fp32")
+    F = torch.from_numpy(cfg["F"]).cuda()
+    Wd = torch.from_numpy(W).cuda()
+    for p, q in [(0, 1), (1, 1)]:
+        gf, gq = dgfs.collide_vjp(pl, p, q, F[:, p], F[:, q], Wd)
+        torch.cuda.synchronize()
+        rf, rq = oracle_vjp(opl[p][q], cfg["F"][0, p], cfg["F"][0, q], W[0])
+        ef, eq = rel_linf(gf[0].cpu().numpy(), rf), rel_linf(gq[0].cpu().numpy(), rq)
+        print("fp32-mixed vjp (%d,%d): rel Linf %.3e %.3e" % (p, q, ef, eq))
+        assert ef <= 1e-5 and eq <= 1e-5, (p, q, ef, eq)
+
+
 @pytest.mark.parametrize("n_nodes,n_dirs", [(4, 16), (256, 64)])
 def test_vjp_central_differences_N32(torch_cuda, n_nodes, n_dirs):
     """Two species (masses 1, 2.5), N = 32, icosahedron, N_rho = 16, on 4
