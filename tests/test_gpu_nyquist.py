@@ -188,7 +188,8 @@ def test_vss_plan_with_the_variant(torch_cuda):
             assert rel_linf(got[i], ref) <= TOL, (p, q, i)
 
 
-def test_batched_with_the_variant_equals_single_calls(torch_cuda):
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_batched_with_the_variant_equals_single_calls(torch_cuda, precision):
     """Instances with and without the option (N 16, 24, 32) in one batched
     launch, bit-identical to one dgfs_collide call per item."""
     from paper_1903_04670_amd import dgfs
@@ -196,7 +197,7 @@ def test_batched_with_the_variant_equals_single_calls(torch_cuda):
     plans, items, outs_b, outs_s = [], [], [], []
     for k, (N, nyq) in enumerate([(16, True), (24, False), (32, True), (24, True)]):
         cfg = small_config(N, ns=2, Nrho=3, seed=80 + k, n_nodes=2)
-        pl = gpu_plan(cfg, nyquist_zero=nyq)
+        pl = gpu_plan(cfg, precision=precision, nyquist_zero=nyq)
         plans.append(pl)
         F = torch.from_numpy(cfg["F"]).cuda()
         for p in range(2):
