@@ -155,3 +155,25 @@ def test_autotune_schedule(torch_cuda, tmp_path, monkeypatch):
     assert torch.equal(again, ref)
     pl2 = gpu_plan(cfg)  # picks the cached schedule up
     assert torch.equal(dgfs.collide(pl2, 0, 1, F[:, 0], F[:, 1]), ref)
+
+
+def test_equilibrium_residual_decays_through_N56(torch_cuda):
+    """Q(M_p, M_q) vanishes for Maxwellians at a common bulk velocity and
+    temperature, and the discrete operator's residual falls spectrally with
+    N: two species (masses 1, 2), S = 4, icosahedron, N_rho = N/2, on
+    N = 24, 32, 40, 48, 56 (the radix-5 and radix-7 grids included).  The
+    residual must fall at every step and by more than 10x from 32 to 56."""
+    from paper_1903_04670_amd import dgfs
+    torch = torch_cuda
+    res = []
+    for N in (24, 32, 40, 48, 56):
+        L, R = wl.box_for_support(4.0)
+        pl = dgfs.Plan([1.0, 2.0], np.full((2, 2), 0.5), np.ones((2, 2)), N, L, N // 2,
+                       sphere="icosahedron", R=np.full((2, 2), R))
+        u, T = (0.3, -0.2, 0.1), 1.0
+        F = np.stack([wl.maxwellian(N, L, 1.0, 1.0, u, T), wl.maxwellian(N, L, 2.0, 0.7, u, T)])[None]
+        Q = run_gpu(torch, pl, F, 0, 1)[0]
+        res.append(float(np.max(np.abs(Q))))
+    print("equilibrium residual max|Q| by N:", ["%.3e" % r for r in res])
+    assert all(a > b for a, b in zip(res, res[1:])), res
+    assert res[-1] < res[1] / 10, res
