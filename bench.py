@@ -362,7 +362,7 @@ def main():
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU only: the collision hot path is benchmarked on a single "
-              "MI355X (multi-GPU sharding is a design note, not part of this build).", file=sys.stderr)
+              "MI355X; sharding across GPUs is described in the design notes, not implemented.", file=sys.stderr)
         sys.exit(2)
     cfg, evals_per_step, res = run(args)
     r64, r32 = res["fp64"], res["fp32"]
