@@ -37,10 +37,11 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--workload", default="couette", choices=["couette", "vjp", "batched", "vss"],
+    ap.add_argument("--workload", default="couette", choices=["couette", "vjp", "batched", "vss", "table1"],
                     help="couette: the headline line (default); vjp: adjoint throughput, 2 species N = 32; "
                          "batched: 1024 uneven instances in one launch per stage vs per-instance launches; "
-                         "vss: three-species VSS N = 48, M = 32, N_rho = 24")
+                         "vss: three-species VSS N = 48, M = 32, N_rho = 24; "
+                         "table1: latency and 64-node throughput at the accuracy study's shapes")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device copy (reference for HBM byte counters)")
     return ap.parse_args()
@@ -347,6 +348,43 @@ def bench_vss(args):
             "data": "synthetic", "config": {"workload": cfg["name"], "nodes": 4, "pairs": 9}}
 
 
+# Table 1 cells whose P100 FP64 time per evaluation the paper prints
+# (Sec. 3.2, Table 1): (N, N_rho, M, seconds).  Context only.
+TABLE1_TIMES = [(16, 8, 6, 0.00056), (16, 8, 12, 0.00085), (24, 6, 12, 0.00114), (32, 8, 12, 0.00287),
+                (32, 16, 12, 0.00541), (32, 32, 12, 0.01057), (48, 24, 12, 0.02556), (56, 56, 12, 0.09303)]
+
+
+def bench_table1(args):
+    """The accuracy study's shapes (equal masses, L = 12, constant kernel:
+    omega = 1) in FP64: the latency of one evaluation (one node, one ordered
+    pair, one call) and the throughput of 64 nodes in one call, beside the
+    paper's printed time per evaluation on its GPU (another machine:
+    context, not a target).  The input is a Maxwellian; the time does not
+    depend on the values."""
+    import numpy as np
+    import torch
+    from paper_1903_04670_amd import dgfs, workloads as wl
+    rows = []
+    for N, Nr, M, paper_s in TABLE1_TIMES:
+        f = wl.maxwellian(N, 12.0, 1.0)
+        plan = dgfs.Plan([1.0, 1.0], np.ones((2, 2)), np.ones((2, 2)), N, 12.0, Nr,
+                         sphere="octahedron" if M == 6 else "icosahedron")
+        one = torch.from_numpy(f[None]).cuda()
+        many = one.expand(64, N, N, N).contiguous()
+        ws1, ws64 = dgfs.workspace(plan, 1), dgfs.workspace(plan, 64)
+        o1, o64 = torch.empty_like(one), torch.empty_like(many)
+        t1 = _time_cuda(lambda: dgfs.collide(plan, 0, 1, one, one, out=o1, ws=ws1), 20, 3)
+        t64 = _time_cuda(lambda: dgfs.collide(plan, 0, 1, many, many, out=o64, ws=ws64), 5, 1)
+        rows.append({"N": N, "N_rho": Nr, "M": M, "latency_ms": round(t1 * 1e3, 4),
+                     "evals_per_s_64_nodes": round(64 / t64, 1), "paper_ms_per_eval": paper_s * 1e3})
+        del plan, ws1, ws64
+        torch.cuda.empty_cache()
+    return {"metric": "Table 1 shapes: latency of one evaluation and 64-node throughput (FP64)",
+            "value": rows[4]["evals_per_s_64_nodes"], "unit": "collision evals/s (N=32, N_rho=16, M=12, 64 nodes)",
+            "rows": rows, "n_gpus": 1, "dtype": "f64", "data": "synthetic (Maxwellian)",
+            "config": {"workload": "accuracy-study shapes, equal masses, omega = 1, L = 12"}}
+
+
 def main():
     args = parse()
     if args.copy_calibration:
@@ -356,7 +394,7 @@ def main():
         if args.gpus != 1:
             print("bench.py measures one GPU only.", file=sys.stderr)
             sys.exit(2)
-        fn = {"vjp": bench_vjp, "batched": bench_batched, "vss": bench_vss}[args.workload]
+        fn = {"vjp": bench_vjp, "batched": bench_batched, "vss": bench_vss, "table1": bench_table1}[args.workload]
         print(json.dumps(fn(args)), flush=True)
         return
     world = int(os.environ.get("WORLD_SIZE", "1"))
