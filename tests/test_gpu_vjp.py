@@ -90,6 +90,29 @@ def test_fp32_mixed_vjp_error_bound(torch_cuda):
         assert ef <= 1e-5 and eq <= 1e-5, (p, q, ef, eq)
 
 
+def test_fp32_mixed_vss_vjp_error_bound(torch_cuda):
+    """The VSS adjoint of an FP32-mixed plan (complex direction tables in
+    FP32) against the FP64 oracle's gradient at N = 12, Fibonacci M = 7,
+    alpha = 1.3: within 1e-5 of the largest gradient entry, as for the VHS
+    FP32-mixed adjoint (a shorter transform chain at N = 12)."""
+    from paper_1903_04670_amd import dgfs
+    torch = torch_cuda
+    cfg = small_config(12, ns=2, M_kind="fibonacci", Nrho=3, seed=44, n_nodes=1)
+    cfg["alpha"] = np.full((2, 2), 1.3)
+    W = np.random.default_rng(9).standard_normal((1, 12, 12, 12))
+    opl = oracle_pairs(cfg)
+    pl = gpu_plan(cfg, precision="fp32")
+    F = torch.from_numpy(cfg["F"]).cuda()
+    Wd = torch.from_numpy(W).cuda()
+    for p, q in [(0, 1), (1, 1)]:
+        gf, gq = dgfs.collide_vjp(pl, p, q, F[:, p], F[:, q], Wd)
+        torch.cuda.synchronize()
+        rf, rq = oracle_vjp(opl[p][q], cfg["F"][0, p], cfg["F"][0, q], W[0])
+        ef, eq = rel_linf(gf[0].cpu().numpy(), rf), rel_linf(gq[0].cpu().numpy(), rq)
+        print("fp32-mixed vss vjp (%d,%d): rel Linf %.3e %.3e" % (p, q, ef, eq))
+        assert ef <= 1e-5 and eq <= 1e-5, (p, q, ef, eq)
+
+
 @pytest.mark.parametrize("n_nodes,n_dirs", [(4, 16), (256, 64)])
 def test_vjp_central_differences_N32(torch_cuda, n_nodes, n_dirs):
     """Two species (masses 1, 2.5), N = 32, icosahedron, N_rho = 16, on 4
