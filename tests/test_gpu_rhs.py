@@ -182,6 +182,28 @@ def test_ssp_rk3_graph_steps_with_the_nyquist_zero_option(torch_cuda):
         assert rel_linf(F.cpu().numpy(), ref) <= 1e-12, k
 
 
+def test_ssp_rk3_graph_steps_with_a_vss_plan(torch_cuda):
+    """Graph-replayed SSP-RK3 steps of the Couette setup with a VSS plan
+    (alpha = 1.4, Fibonacci M = 7: the direction-dependent gain kernels
+    inside the captured graph), against the oracle."""
+    from paper_1903_04670_amd import dgfs
+    torch = torch_cuda
+    cfg = _couette_small(seed=13)
+    cfg = dict(cfg, alpha=np.full((2, 2), 1.4), sphere="fibonacci", M=7)
+    prob, coll = _oracle_rhs(cfg, cfg["F"], project=True)
+    pl = gpu_plan(cfg, dg_order=cfg["P"])
+    mesh = dgfs.make_mesh(cfg["K"])
+    F = torch.from_numpy(cfg["F"]).cuda()
+    ws = dgfs.workspace(pl, F.shape[0], dgfs.OP_STEP)
+    ref = cfg["F"].copy()
+    dt = 2e-3
+    for k in range(2):
+        dgfs.step(pl, F, dt, 1, mesh=mesh, project=True, ws=ws)
+        torch.cuda.synchronize()
+        ref = odg.ssp_rk3(ref, dt, lambda X: prob.rhs(X, coll))
+        assert rel_linf(F.cpu().numpy(), ref) <= 1e-12, k
+
+
 def test_argument_errors_are_reported(torch_cuda):
     from paper_1903_04670_amd import dgfs
     torch = torch_cuda
