@@ -207,3 +207,30 @@ def test_conservation_residual_decays_through_N56(torch_cuda):
     print("conservation residual by N:", ["%.3e" % r for r in out])
     assert out[0] > out[1] > out[2], out
     assert abs(out[4] - out[3]) < 0.02 * out[4] and out[4] < 1e-3, out
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_check_flag_passes_finite_and_reports_nonfinite(torch_cuda, precision):
+    """DGFS_CHECK: on finite input the result is the unchecked one bit for
+    bit; with a NaN planted in one node's f^p every value of that node's
+    output is non-finite (the transform spreads it), the other node stays
+    finite, and the call returns DGFS_ENONFINITE with the count."""
+    from paper_1903_04670_amd import dgfs
+    torch = torch_cuda
+    cfg = small_config(8, ns=2, M_kind="icosahedron", Nrho=3, seed=5, n_nodes=2)
+    pl = gpu_plan(cfg, precision=precision)
+    plain = run_gpu(torch, pl, cfg["F"], 0, 1)
+    checked = run_gpu(torch, pl, cfg["F"], 0, 1, check=True)
+    assert np.array_equal(plain, checked)
+    F = cfg["F"].copy()
+    F[1, 0, 3, 2, 5] = np.nan
+    Fd = torch.from_numpy(F).cuda()
+    out = torch.zeros((2, 8, 8, 8), dtype=torch.float64, device="cuda")
+    with pytest.raises(dgfs.DGFSError) as ei:
+        dgfs.collide(pl, 0, 1, Fd[:, 0], Fd[:, 1], out=out, check=True)
+    torch.cuda.synchronize()
+    assert ei.value.status == dgfs.ENONFINITE
+    assert "%d non-finite" % 8 ** 3 in str(ei.value)
+    got = out.cpu().numpy()
+    assert np.isfinite(got[0]).all() and not np.isfinite(got[1]).any()
+    assert rel_linf(got[0], plain[0]) == 0.0

@@ -217,3 +217,33 @@ def test_argument_errors_are_reported(torch_cuda):
     with pytest.raises(dgfs.DGFSError) as ei:
         dgfs.rhs(pl, F, mesh=dgfs.make_mesh(cfg["K"]), ws=ws)
     assert ei.value.status == dgfs.EWORKSPACE
+
+
+def test_check_flag_on_rhs_and_step(torch_cuda):
+    """DGFS_CHECK on dgfs_rhs and dgfs_step: finite states pass with results
+    equal bit for bit to the unchecked calls; a NaN planted in one node of
+    the state makes both calls return DGFS_ENONFINITE."""
+    from paper_1903_04670_amd import dgfs
+    torch = torch_cuda
+    cfg = _couette_small()
+    pl = gpu_plan(cfg, dg_order=cfg["P"])
+    mesh = dgfs.make_mesh(cfg["K"])
+    F = torch.from_numpy(cfg["F"]).cuda()
+    a = dgfs.rhs(pl, F, mesh=mesh).cpu().numpy()
+    b = dgfs.rhs(pl, F, mesh=mesh, check=True).cpu().numpy()
+    assert np.array_equal(a, b)
+    F1, F2 = F.clone(), F.clone()
+    dgfs.step(pl, F1, 1e-3, 1, mesh=mesh)
+    dgfs.step(pl, F2, 1e-3, 1, mesh=mesh, check=True)
+    torch.cuda.synchronize()
+    assert torch.equal(F1, F2)
+    bad = cfg["F"].copy()
+    bad[4, 1, 1, 6, 2] = np.nan
+    Fb = torch.from_numpy(bad).cuda()
+    with pytest.raises(dgfs.DGFSError) as ei:
+        dgfs.rhs(pl, Fb, mesh=mesh, check=True)
+    assert ei.value.status == dgfs.ENONFINITE
+    with pytest.raises(dgfs.DGFSError) as ei:
+        dgfs.step(pl, Fb, 1e-3, 1, mesh=mesh, check=True)
+    assert ei.value.status == dgfs.ENONFINITE
+    torch.cuda.synchronize()
