@@ -209,6 +209,10 @@ dgfs_status dgfs_step(dgfs_plan plan, const dgfs_mesh *mesh, int64_t n_nodes,
  *   items[n_items]  host array; item i evaluates Q^{pq} of plans[plan] on
  *                   n_nodes nodes, like dgfs_collide
  * The results equal those of one dgfs_collide call per item bit for bit.
+ * Items run concurrently: the output ranges of different items must not
+ * share an element (with or without DGFS_ACCUMULATE); interleaved strided
+ * outputs that touch distinct elements are fine.  Items with n_nodes == 0
+ * are skipped.  flags: DGFS_ACCUMULATE only.
  */
 typedef struct {
   int32_t plan;

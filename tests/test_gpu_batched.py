@@ -123,3 +123,41 @@ def test_batched_radix5_radix7_grids_equal_single_calls(torch_cuda, precision):
         ref = oracle_collide(oracle_pairs(cfg)[0][0], cfg["F"][0, 0], cfg["F"][0, 0])
         got = [ob for (k, p, q, _, _, ob) in items if k == 3][0].cpu().numpy()[0]
         assert rel_linf(got, ref) <= 1e-11
+
+
+def test_batched_accumulate_empty_items_and_strided_outputs(torch_cuda):
+    """DGFS_ACCUMULATE on a batch equals one accumulating dgfs_collide per
+    item bit for bit; items with zero nodes are skipped (alone, a batch of
+    them is a no-op); outputs may be node-strided views of a species-major
+    array."""
+    from paper_1903_04670_amd import dgfs
+    torch = torch_cuda
+    rng = np.random.default_rng(21)
+    insts = [small_config(8, ns=2, Nrho=3, seed=61, n_nodes=3),
+             small_config(12, ns=1, Nrho=3, seed=62, n_nodes=2, M_kind="octahedron"),
+             small_config(16, ns=2, Nrho=2, seed=63, n_nodes=1, M_kind="fibonacci")]
+    plans = [gpu_plan(cfg) for cfg in insts]
+    items, outs_b, outs_s = [], [], []
+    for k, cfg in enumerate(insts):
+        F = torch.from_numpy(cfg["F"]).cuda()
+        ns, N = cfg["ns"], cfg["N"]
+        shape = (cfg["n_nodes"], ns * ns, N, N, N)
+        base = torch.from_numpy(rng.standard_normal(shape) * 1e-3).cuda()
+        Ob, Os = base.clone(), base.clone()      # out[:, p * ns + q] is node-strided; no two items share one
+        for p in range(ns):
+            for q in range(ns):
+                items.append((k, p, q, F[:, p], F[:, q], Ob[:, p * ns + q]))
+                dgfs.collide(plans[k], p, q, F[:, p], F[:, q], out=Os[:, p * ns + q], accumulate=True)
+        items.append((k, 0, 0, F[:0, 0], F[:0, 0], Ob[:0, 0]))   # zero nodes
+        outs_b.append(Ob)
+        outs_s.append(Os)
+    dgfs.collide_batched(plans, items, accumulate=True)
+    torch.cuda.synchronize()
+    for Ob, Os in zip(outs_b, outs_s):
+        assert torch.equal(Ob, Os)
+    # a batch of empty items leaves everything as it was
+    before = [o.clone() for o in outs_b]
+    dgfs.collide_batched(plans, [it for it in items if it[3].shape[0] == 0])
+    torch.cuda.synchronize()
+    for o, b in zip(outs_b, before):
+        assert torch.equal(o, b)
