@@ -136,73 +136,80 @@ extern "C" dgfs_status dgfs_collide_batched(const dgfs_plan *plans, int32_t n_pl
   if (!g_stage_done && (e = hipEventCreateWithFlags(&g_stage_done, hipEventDisableTiming)) != hipSuccess)
     return hip_status(e, "batched staging");
   char *wsb = static_cast<char *>(ws);
-  size_t begin = 0;
-  for (size_t c = 0; c < ends.size(); ++c) {
-    const size_t end = ends[c], n = end - begin;
-    char *host = static_cast<char *>(g_stage) + c * desc_bytes;
-    SubItem *hi = reinterpret_cast<SubItem *>(host);
-    int *hs = reinterpret_cast<int *>(host + a256(max_count * sizeof(SubItem)));
-    char *region = wsb + desc_bytes;
-    int total[kStages] = {0, 0, 0, 0, 0};
-    for (size_t k = 0; k < n; ++k) {
-      const SubRef &r = subs[begin + k];
-      const dgfs_item &it = items[r.item];
-      const dgfs_plan_s *pl = plans[it.plan];
-      const int nz = (it.p == it.q && it.fp == it.fq) ? 1 : 2;
-      SubItem si{};
-      pipeline_common(pl, si.a);
-      pipeline_carve(pl, r.nb, 1, nz, region, si.a);
-      region += r.bytes;
-      si.a.n_nodes = r.nb;
-      si.a.n_pairs = 1;
-      si.a.nz = nz;
-      si.a.pair_id[0] = it.p * pl->ns + it.q;
-      si.a.zp[0] = 0;
-      si.a.zq[0] = nz == 1 ? 0 : 1;
-      si.a.xshare[0] = nz == 1 ? 1 : 0;
-      pipeline_slots(pl, si.a);
-      si.fw.src[0] = it.fp + r.n0 * it.node_stride;
-      si.fw.src[1] = it.fq + r.n0 * it.node_stride;
-      si.fw.node_stride = it.node_stride;
-      si.fw.n_nodes = r.nb;
-      si.fw.nz = nz;
-      si.fw.Z = si.a.Z;
-      si.fa.n_out = 1;
-      si.fa.qcount = 1;
-      si.fa.fsrc[0] = it.fp + r.n0 * it.node_stride;
-      si.fa.f_stride = it.node_stride;
-      si.fa.out[0] = it.Q + r.n0 * it.out_stride;
-      si.fa.out_stride = it.out_stride;
-      si.fa.accumulate = (flags & DGFS_ACCUMULATE) ? 1 : 0;
-      si.N = pl->N;
-      si.vss = pl->vhs ? 0 : 1;
-      hi[k] = si;
-      for (int sg = 0; sg < kStages; ++sg) {
-        hs[sg * (n + 1) + k] = total[sg];
-        total[sg] += blocks_of(sg, si);
+  // enqueue every chunk; the staging event is recorded whatever the outcome,
+  // so the next call never rewrites descriptors a pending copy still reads
+  auto enqueue = [&]() -> dgfs_status {
+    hipError_t e = hipSuccess;
+    size_t begin = 0;
+    for (size_t c = 0; c < ends.size(); ++c) {
+      const size_t end = ends[c], n = end - begin;
+      char *host = static_cast<char *>(g_stage) + c * desc_bytes;
+      SubItem *hi = reinterpret_cast<SubItem *>(host);
+      int *hs = reinterpret_cast<int *>(host + a256(max_count * sizeof(SubItem)));
+      char *region = wsb + desc_bytes;
+      int total[kStages] = {0, 0, 0, 0, 0};
+      for (size_t k = 0; k < n; ++k) {
+        const SubRef &r = subs[begin + k];
+        const dgfs_item &it = items[r.item];
+        const dgfs_plan_s *pl = plans[it.plan];
+        const int nz = (it.p == it.q && it.fp == it.fq) ? 1 : 2;
+        SubItem si{};
+        pipeline_common(pl, si.a);
+        pipeline_carve(pl, r.nb, 1, nz, region, si.a);
+        region += r.bytes;
+        si.a.n_nodes = r.nb;
+        si.a.n_pairs = 1;
+        si.a.nz = nz;
+        si.a.pair_id[0] = it.p * pl->ns + it.q;
+        si.a.zp[0] = 0;
+        si.a.zq[0] = nz == 1 ? 0 : 1;
+        si.a.xshare[0] = nz == 1 ? 1 : 0;
+        pipeline_slots(pl, si.a);
+        si.fw.src[0] = it.fp + r.n0 * it.node_stride;
+        si.fw.src[1] = it.fq + r.n0 * it.node_stride;
+        si.fw.node_stride = it.node_stride;
+        si.fw.n_nodes = r.nb;
+        si.fw.nz = nz;
+        si.fw.Z = si.a.Z;
+        si.fa.n_out = 1;
+        si.fa.qcount = 1;
+        si.fa.fsrc[0] = it.fp + r.n0 * it.node_stride;
+        si.fa.f_stride = it.node_stride;
+        si.fa.out[0] = it.Q + r.n0 * it.out_stride;
+        si.fa.out_stride = it.out_stride;
+        si.fa.accumulate = (flags & DGFS_ACCUMULATE) ? 1 : 0;
+        si.N = pl->N;
+        si.vss = pl->vhs ? 0 : 1;
+        hi[k] = si;
+        for (int sg = 0; sg < kStages; ++sg) {
+          hs[sg * (n + 1) + k] = total[sg];
+          total[sg] += blocks_of(sg, si);
+        }
       }
+      for (int sg = 0; sg < kStages; ++sg) hs[sg * (n + 1) + n] = total[sg];
+      // descriptors to the head of the workspace, then the five stage launches
+      SubItem *d_items = reinterpret_cast<SubItem *>(wsb);
+      int *d_start = reinterpret_cast<int *>(wsb + a256(max_count * sizeof(SubItem)));
+      if ((e = hipMemcpyAsync(d_items, hi, n * sizeof(SubItem), hipMemcpyHostToDevice, st)) != hipSuccess)
+        return hip_status(e, "batched descriptors");
+      if ((e = hipMemcpyAsync(d_start, hs, kStages * (n + 1) * sizeof(int), hipMemcpyHostToDevice, st)) != hipSuccess)
+        return hip_status(e, "batched descriptors");
+      // the start arrays were laid out with stride (n + 1) per stage
+      const bool f64 = plans[0]->precision == DGFS_FP64;
+      if (nmax <= 16) e = f64 ? launch_batch<double, 16>(d_items, d_start, total, (int)n, elt, st)
+                              : launch_batch<float, 16>(d_items, d_start, total, (int)n, elt, st);
+      else if (nmax <= 32) e = f64 ? launch_batch<double, 32>(d_items, d_start, total, (int)n, elt, st)
+                                   : launch_batch<float, 32>(d_items, d_start, total, (int)n, elt, st);
+      else if (nmax <= 48) e = f64 ? launch_batch<double, 48>(d_items, d_start, total, (int)n, elt, st)
+                                   : launch_batch<float, 48>(d_items, d_start, total, (int)n, elt, st);
+      else e = f64 ? launch_batch<double, 56>(d_items, d_start, total, (int)n, elt, st)
+                   : launch_batch<float, 56>(d_items, d_start, total, (int)n, elt, st);
+      if (e != hipSuccess) return hip_status(e, "dgfs_collide_batched launch");
+      begin = end;
     }
-    for (int sg = 0; sg < kStages; ++sg) hs[sg * (n + 1) + n] = total[sg];
-    // descriptors to the head of the workspace, then the five stage launches
-    SubItem *d_items = reinterpret_cast<SubItem *>(wsb);
-    int *d_start = reinterpret_cast<int *>(wsb + a256(max_count * sizeof(SubItem)));
-    if ((e = hipMemcpyAsync(d_items, hi, n * sizeof(SubItem), hipMemcpyHostToDevice, st)) != hipSuccess)
-      return hip_status(e, "batched descriptors");
-    if ((e = hipMemcpyAsync(d_start, hs, kStages * (n + 1) * sizeof(int), hipMemcpyHostToDevice, st)) != hipSuccess)
-      return hip_status(e, "batched descriptors");
-    // the start arrays were laid out with stride (n + 1) per stage
-    const bool f64 = plans[0]->precision == DGFS_FP64;
-    if (nmax <= 16) e = f64 ? launch_batch<double, 16>(d_items, d_start, total, (int)n, elt, st)
-                            : launch_batch<float, 16>(d_items, d_start, total, (int)n, elt, st);
-    else if (nmax <= 32) e = f64 ? launch_batch<double, 32>(d_items, d_start, total, (int)n, elt, st)
-                                 : launch_batch<float, 32>(d_items, d_start, total, (int)n, elt, st);
-    else if (nmax <= 48) e = f64 ? launch_batch<double, 48>(d_items, d_start, total, (int)n, elt, st)
-                                 : launch_batch<float, 48>(d_items, d_start, total, (int)n, elt, st);
-    else e = f64 ? launch_batch<double, 56>(d_items, d_start, total, (int)n, elt, st)
-                 : launch_batch<float, 56>(d_items, d_start, total, (int)n, elt, st);
-    if (e != hipSuccess) return hip_status(e, "dgfs_collide_batched launch");
-    begin = end;
-  }
-  if ((e = hipEventRecord(g_stage_done, st)) != hipSuccess) return hip_status(e, "batched staging");
-  return DGFS_OK;
+    return DGFS_OK;
+  };
+  const dgfs_status st_enq = enqueue();
+  if ((e = hipEventRecord(g_stage_done, st)) != hipSuccess && st_enq == DGFS_OK) return hip_status(e, "batched staging");
+  return st_enq;
 }
