@@ -24,6 +24,9 @@ size_t pipeline_bytes(const dgfs_plan_s *pl, int B, int n_pairs, int nz);
 
 static std::mutex g_tune_mu;
 
+// evaluations per launch the tuner tries (powers of two in this range)
+constexpr int kTuneMin = 8, kTuneMax = 256;
+
 static std::string cache_path() {
   if (const char *p = std::getenv("DGFS_TUNE_CACHE")) return p;
   const char *home = std::getenv("HOME");
@@ -52,7 +55,10 @@ void load_tuned(dgfs_plan_s *pl) {
   while (std::getline(in, line)) {
     const size_t bar = line.rfind('|');
     if (bar == std::string::npos) continue;
-    if (line.substr(0, bar) == key) pl->chunk_evals = std::atoi(line.c_str() + bar + 1);  // last entry wins
+    if (line.substr(0, bar) != key) continue;
+    // last entry wins; a value outside the tuner's candidate range is ignored
+    const int v = std::atoi(line.c_str() + bar + 1);
+    if (v >= kTuneMin && v <= kTuneMax) pl->chunk_evals = v;
   }
 }
 
@@ -79,11 +85,13 @@ extern "C" dgfs_status dgfs_autotune(dgfs_plan pl, int64_t n_nodes, int32_t p, i
   const int saved = pl->chunk_evals;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   hipError_t he;
-  if ((he = hipEventCreate(&e0)) != hipSuccess || (he = hipEventCreate(&e1)) != hipSuccess)
+  if ((he = hipEventCreate(&e0)) != hipSuccess || (he = hipEventCreate(&e1)) != hipSuccess) {
+    if (e0) (void)hipEventDestroy(e0);
     return hip_status(he, "dgfs_autotune events");
+  }
   float best = 0.0f;
   int best_e = 0;
-  for (int E : {8, 16, 32, 64, 128, 256}) {
+  for (int E = kTuneMin; E <= kTuneMax; E *= 2) {
     if (E > 2 * n_nodes && E > 8) break;
     if (pipeline_bytes(pl, (int)std::min<int64_t>(E, n_nodes), 1, nz) > ws_bytes) continue;
     pl->chunk_evals = E;
@@ -100,6 +108,8 @@ extern "C" dgfs_status dgfs_autotune(dgfs_plan pl, int64_t n_nodes, int32_t p, i
     (void)hipEventRecord(e1, st);
     if ((he = hipEventSynchronize(e1)) != hipSuccess) {
       pl->chunk_evals = saved;
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
       return hip_status(he, "dgfs_autotune");
     }
     float ms = 0.0f;

@@ -155,6 +155,12 @@ def test_autotune_schedule(torch_cuda, tmp_path, monkeypatch):
     assert torch.equal(again, ref)
     pl2 = gpu_plan(cfg)  # picks the cached schedule up
     assert torch.equal(dgfs.collide(pl2, 0, 1, F[:, 0], F[:, 1]), ref)
+    # entries outside the candidate range are ignored when a plan loads the cache
+    key = (tmp_path / "tune.txt").read_text().strip().rsplit("|", 1)[0]
+    with open(tmp_path / "tune.txt", "a") as fh:
+        fh.write("%s|0\n%s|-7\n%s|999999\n%s|x\n" % (key, key, key, key))
+    pl3 = gpu_plan(cfg)
+    assert torch.equal(dgfs.collide(pl3, 0, 1, F[:, 0], F[:, 1]), ref)
 
 
 def test_equilibrium_residual_decays_through_N56(torch_cuda):
