@@ -39,28 +39,29 @@ __device__ __forceinline__ double wall_maxwellian(double m, const double *u, dou
 
 // Wall densities n_w from zero discrete net mass flux (one block per wall and
 // species; fixed-order reduction).
-__global__ void __launch_bounds__(256) k_wall_density(DGArgs a, double *nw) {
+constexpr int kWallThreads = 1024;
+
+__global__ void __launch_bounds__(kWallThreads) k_wall_density(DGArgs a, double *nw) {
   const int wall = blockIdx.x / a.ns, p = blockIdx.x % a.ns;
   const int N = a.N, n3 = N * N * N;
   const int node = wall == 0 ? 0 : a.K * (a.P + 1) - 1;
   const double *f = a.F + ((size_t)node * a.ns + p) * n3;
   double out = 0.0, unit = 0.0;
-  for (int v = threadIdx.x; v < n3; v += blockDim.x) {
+  for (int v = threadIdx.x; v < n3; v += kWallThreads) {
     const double cx = grid_c(v / (N * N), N, a.L), cy = grid_c((v / N) % N, N, a.L), cz = grid_c(v % N, N, a.L);
-    const double mw = wall_maxwellian(a.mass[p], a.uw[wall], a.Tw[wall], cx, cy, cz);
     if (wall == 0) {  // emits c_x > 0, absorbs c_x < 0
       if (cx < 0) out -= cx * f[v];
-      else unit += cx * mw;
+      else unit += cx * wall_maxwellian(a.mass[p], a.uw[wall], a.Tw[wall], cx, cy, cz);
     } else {
       if (cx > 0) out += cx * f[v];
-      else unit -= cx * mw;
+      else unit -= cx * wall_maxwellian(a.mass[p], a.uw[wall], a.Tw[wall], cx, cy, cz);
     }
   }
-  __shared__ double so[256], su[256];
+  __shared__ double so[kWallThreads], su[kWallThreads];
   so[threadIdx.x] = out;
   su[threadIdx.x] = unit;
   __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
+  for (int s = kWallThreads / 2; s > 0; s >>= 1) {
     if (threadIdx.x < s) {
       so[threadIdx.x] += so[threadIdx.x + s];
       su[threadIdx.x] += su[threadIdx.x + s];
@@ -71,25 +72,33 @@ __global__ void __launch_bounds__(256) k_wall_density(DGArgs a, double *nw) {
 }
 
 // dF/dt = -c_x dF/dx by nodal DG (strong form, upwind flux).  One thread per
-// (species, velocity point), looping over the elements.
+// (species, velocity point, element); blockIdx.y strides over the elements.
 __global__ void __launch_bounds__(256) k_dg_transport(DGArgs a) {
   const int N = a.N, n3 = N * N * N, P = a.P, np1 = a.P + 1;
   const int v = blockIdx.x * blockDim.x + threadIdx.x;
-  const int p = blockIdx.y;
+  const int p = blockIdx.z;
   if (v >= n3) return;
-  const double cx = grid_c(v / (N * N), N, a.L), cy = grid_c((v / N) % N, N, a.L), cz = grid_c(v % N, N, a.L);
+  const double cx = grid_c(v / (N * N), N, a.L);
   const size_t ns_stride = (size_t)a.ns * n3;
   const double *f = a.F + (size_t)p * n3 + v;
   double *df = a.dF + (size_t)p * n3 + v;
-  const int nodes = a.K * np1;
-  const double gL = cx > 0 ? a.nw[p] * wall_maxwellian(a.mass[p], a.uw[0], a.Tw[0], cx, cy, cz) : 0.0;
-  const double gR = cx < 0 ? a.nw[a.ns + p] * wall_maxwellian(a.mass[p], a.uw[1], a.Tw[1], cx, cy, cz) : 0.0;
   const double s = 2.0 / a.h;
-  for (int e = 0; e < a.K; ++e) {
+  for (int e = blockIdx.y; e < a.K; e += gridDim.y) {
     double u[kMaxDG];
     for (int i = 0; i <= P; ++i) u[i] = f[(size_t)(e * np1 + i) * ns_stride];
-    const double uL = e == 0 ? gL : f[(size_t)(e * np1 - 1) * ns_stride];
-    const double uR = e == a.K - 1 ? gR : f[(size_t)((e + 1) * np1) * ns_stride];
+    double uL, uR;
+    if (e == 0) {
+      const double cy = grid_c((v / N) % N, N, a.L), cz = grid_c(v % N, N, a.L);
+      uL = cx > 0 ? a.nw[p] * wall_maxwellian(a.mass[p], a.uw[0], a.Tw[0], cx, cy, cz) : 0.0;
+    } else {
+      uL = f[(size_t)(e * np1 - 1) * ns_stride];
+    }
+    if (e == a.K - 1) {
+      const double cy = grid_c((v / N) % N, N, a.L), cz = grid_c(v % N, N, a.L);
+      uR = cx < 0 ? a.nw[a.ns + p] * wall_maxwellian(a.mass[p], a.uw[1], a.Tw[1], cx, cy, cz) : 0.0;
+    } else {
+      uR = f[(size_t)((e + 1) * np1) * ns_stride];
+    }
     // boundary terms n (c u - F*) with the upwind flux F*
     const double termR = cx > 0 ? 0.0 : cx * (u[P] - uR);
     const double termL = cx > 0 ? -cx * (u[0] - uL) : 0.0;
@@ -99,7 +108,6 @@ __global__ void __launch_bounds__(256) k_dg_transport(DGArgs a) {
       df[(size_t)(e * np1 + i) * ns_stride] = s * (-cx * d + a.Minv[i * np1 + P] * termR + a.Minv[i * np1] * termL);
     }
   }
-  (void)nodes;
 }
 
 struct ProjArgs {
@@ -274,8 +282,10 @@ static hipError_t enqueue_rhs(const dgfs_plan_s *pl, const dgfs_mesh *mesh, int6
     d.F = F;
     d.dF = dF;
     d.nw = nw;
-    DGFS_LAUNCH("k_wall_density", k_wall_density, dim3(2 * ns), dim3(256), 0, st, d, nw);
-    DGFS_LAUNCH("k_dg_transport", k_dg_transport, dim3((unsigned)((n3 + 255) / 256), ns), dim3(256), 0, st, d);
+    DGFS_LAUNCH("k_wall_density", k_wall_density, dim3(2 * ns), dim3(kWallThreads), 0, st, d, nw);
+    // element slices in y (each thread strides over the rest); species in z
+    const unsigned ey = (unsigned)std::min(mesh->K, 64);
+    DGFS_LAUNCH("k_dg_transport", k_dg_transport, dim3((unsigned)((n3 + 255) / 256), ey, ns), dim3(256), 0, st, d);
   }
   const int npairs = ns * ns;
   PipeArgs a{};
