@@ -72,6 +72,24 @@ def test_couette_rhs_matches_oracle(torch_cuda):
     assert rel_linf(got - mixture_collision(oracle_pairs(cfg), cfg["F"]), tr) <= 1e-10
 
 
+@pytest.mark.parametrize("K,P", [(70, 1), (129, 2)])
+def test_couette_rhs_more_elements_than_grid_slices(torch_cuda, K, P):
+    """The transport kernel spreads the elements over at most 64 slices and
+    each thread strides over the rest: K = 70 and 129 take the second and
+    third passes.  N = 4, one species, against the oracle."""
+    from paper_1903_04670_amd import dgfs
+    torch = torch_cuda
+    cfg = small_config(4, ns=1, M_kind="octahedron", Nrho=2, seed=K, n_nodes=K * (P + 1))
+    cfg.update(K=K, P=P, u_left=(0.0, -0.5, 0.0), u_right=(0.0, 0.5, 0.0))
+    prob, coll = _oracle_rhs(cfg, cfg["F"])
+    ref = prob.rhs(cfg["F"], coll)
+    pl = gpu_plan(cfg, dg_order=P)
+    got = dgfs.rhs(pl, torch.from_numpy(cfg["F"]).cuda(), mesh=dgfs.make_mesh(K)).cpu().numpy()
+    assert rel_linf(got, ref) <= TOL
+    tr = prob.transport_rhs(cfg["F"])
+    assert rel_linf(got - mixture_collision(oracle_pairs(cfg), cfg["F"]), tr) <= 1e-10
+
+
 @pytest.mark.parametrize("sphere", ["icosahedron", "octahedron"])
 def test_symmetric_gain_schedule_three_species(torch_cuda, sphere, monkeypatch):
     """Mixture collision term of three species: the (q, p) gain sums reused
