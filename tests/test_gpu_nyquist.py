@@ -39,7 +39,8 @@ def _collide(torch, plan, F, p, q):
 @pytest.mark.parametrize("N,kind", [(4, "octahedron"), (6, "icosahedron"), (8, "fibonacci"),
                                     (10, "octahedron"), (12, "icosahedron"), (14, "icosahedron"),
                                     (16, "octahedron"), (18, "icosahedron"), (24, "octahedron"),
-                                    (36, "icosahedron"), (40, "octahedron"), (48, "octahedron")])
+                                    (36, "icosahedron"), (40, "octahedron"), (48, "octahedron"),
+                                    (56, "octahedron")])
 def test_packed_gain_small_sizes_all_pairs(torch_cuda, N, kind):
     cfg = small_config(N, ns=2, M_kind=kind, Nrho=3 if N < 16 else 4, seed=60 + N, n_nodes=2)
     opl = oracle_pairs(cfg, nyquist_zero=True)
