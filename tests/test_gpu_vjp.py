@@ -39,6 +39,27 @@ def test_vjp_matches_oracle_gradient(torch_cuda, N, kind):
             assert rel_linf(gq[i].cpu().numpy(), rq) <= 1e-11, (p, q, i)
 
 
+@pytest.mark.parametrize("N", [40, 56])
+def test_vjp_radix5_radix7_grids(torch_cuda, N):
+    """The adjoint on N = 40 = 8 x 5 and N = 56 = 8 x 7 (one node, a cross
+    pair and a self pair, octahedron, N_rho = 2) against the oracle's
+    gradient at 1e-11."""
+    from paper_1903_04670_amd import dgfs
+    torch = torch_cuda
+    cfg = small_config(N, ns=2, M_kind="octahedron", Nrho=2, seed=70 + N, n_nodes=1)
+    W = np.random.default_rng(N + 3).standard_normal((1, N, N, N))
+    opl = oracle_pairs(cfg)
+    pl = gpu_plan(cfg)
+    F = torch.from_numpy(cfg["F"]).cuda()
+    Wd = torch.from_numpy(W).cuda()
+    for p, q in [(0, 1), (1, 1)]:
+        gf, gq = dgfs.collide_vjp(pl, p, q, F[:, p], F[:, q], Wd)
+        torch.cuda.synchronize()
+        rf, rq = oracle_vjp(opl[p][q], cfg["F"][0, p], cfg["F"][0, q], W[0])
+        assert rel_linf(gf[0].cpu().numpy(), rf) <= 1e-11, (N, p, q)
+        assert rel_linf(gq[0].cpu().numpy(), rq) <= 1e-11, (N, p, q)
+
+
 @pytest.mark.parametrize("N,kind,alpha", [(8, "fibonacci", 1.4), (10, "icosahedron", 1.2),
                                           (12, "octahedron", 1.3), (16, "fibonacci", 0.8)])
 def test_vss_vjp_matches_oracle_gradient(torch_cuda, N, kind, alpha):
