@@ -62,6 +62,22 @@ def test_vss_collide_parity(torch_cuda, N, kind, M, alpha):
                 assert rel_linf(got[i], ref) <= TOL, (N, p, q, i)
 
 
+def test_vss_radix5_grid_N40(torch_cuda):
+    """A VSS plan (alpha = 1.3) on N = 40 = 8 x 5: one node, a cross pair and
+    a self pair, octahedron, N_rho = 2, against the oracle at 1e-11 (its
+    direction-dependent tables take about 20 s to build at this size)."""
+    from paper_1903_04670_amd import dgfs
+    torch = torch_cuda
+    cfg = vss_config(40, ns=2, kind="octahedron", Nrho=2, seed=40, n_nodes=1, alpha=1.3)
+    pl = gpu_plan(cfg)
+    opl = oracle_pairs(cfg)
+    F = torch.from_numpy(cfg["F"]).cuda()
+    for p, q in [(0, 1), (1, 1)]:
+        got = dgfs.collide(pl, p, q, F[:, p], F[:, q]).cpu().numpy()
+        ref = oracle_collide(opl[p][q], cfg["F"][0, p], cfg["F"][0, q])
+        assert rel_linf(got[0], ref) <= TOL, (p, q)
+
+
 def test_vss_three_species_rhs_N16(torch_cuda):
     """Three species (masses 1, 2, 4), alpha = 1.4, Fibonacci M = 32,
     N_rho = 8 at N = 16: the mixture collision term against the oracle."""
