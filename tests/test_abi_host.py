@@ -86,6 +86,15 @@ def test_null_arguments():
     assert dgfs.lib.dgfs_collide(None, 1, 0, 0, None, None, 0, None, 0, 0, None, 0, None) == dgfs.EINVAL
     assert dgfs.lib.dgfs_rhs(None, None, 1, None, None, 0, None, 0, None) == dgfs.EINVAL
     assert dgfs.lib.dgfs_workspace_bytes(None, 10, 0) == 0
+    assert dgfs.lib.dgfs_collide_vjp(None, 1, 0, 0, None, None, 0, None, 0, None, None, 0, 0, None, 0,
+                                     None) == dgfs.EINVAL
+    assert dgfs.lib.dgfs_step(None, None, 1, None, 0.1, 1, 0, None, 0, None) == dgfs.EINVAL
+    assert dgfs.lib.dgfs_autotune(None, 1, 0, 0, None, None, 0, None, 0, None, 0, None, None) == dgfs.EINVAL
+    # batched: flags other than DGFS_ACCUMULATE, then NULL plans, are refused
+    assert dgfs.lib.dgfs_collide_batched(None, 1, None, 0, dgfs.CHECK, None, 0, None) == dgfs.EINVAL
+    assert b"flags" in dgfs.lib.dgfs_last_error()
+    assert dgfs.lib.dgfs_collide_batched(None, 1, None, 0, 0, None, 0, None) == dgfs.EINVAL
+    assert dgfs.lib.dgfs_batched_workspace_bytes(None, 1, None, 0) == 0
     dgfs.lib.dgfs_plan_destroy(None)
 
 
