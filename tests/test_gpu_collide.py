@@ -136,6 +136,26 @@ def test_fp32_mixed_error_bound(torch_cuda):
         assert err_q <= 5e-4
 
 
+@pytest.mark.parametrize("N", [40, 56])
+def test_fp32_mixed_radix5_radix7_grids(torch_cuda, N):
+    """FP32-mixed plans on N = 40 and 56 (radix-5 and radix-7 transforms in
+    single precision) against the FP64 oracle, within the same bounds as at
+    N = 32: 2e-6 of the loss term and 5e-4 of Q."""
+    from oracle.collide import collide_gain_loss
+    cfg = small_config(N, ns=2, M_kind="octahedron", Nrho=2, seed=80 + N, n_nodes=1)
+    opl = oracle_pairs(cfg)
+    pl = gpu_plan(cfg, precision="fp32")
+    for p, q in [(0, 1), (1, 1)]:
+        got = run_gpu(torch_cuda, pl, cfg["F"], p, q)
+        gain, loss = collide_gain_loss(opl[p][q], cfg["F"][0, p], cfg["F"][0, q])
+        ref = gain - loss
+        err_q = rel_linf(got[0], ref)
+        err_l = float(np.max(np.abs(got[0] - ref)) / np.max(np.abs(loss)))
+        print("fp32-mixed N=%d (%d,%d): rel to |Q| %.3e, rel to |loss| %.3e" % (N, p, q, err_q, err_l))
+        assert err_l <= 2e-6
+        assert err_q <= 5e-4
+
+
 def test_autotune_schedule(torch_cuda, tmp_path, monkeypatch):
     """The autotuner picks one of its candidate chunk widths, stores it in the
     cache, and the tuned plan gives bit-identical results."""
