@@ -174,6 +174,30 @@ def test_euler_steps_with_mesh_and_projection(torch_cuda):
         assert rel_linf(F.cpu().numpy(), ref) <= 1e-12, k
 
 
+def test_step_graph_recaptured_when_the_call_changes(torch_cuda):
+    """The captured step is keyed by (mesh, nodes, state pointer, dt, flags,
+    workspace): calls alternating dt, then a second state array, are each
+    recaptured and match the oracle's SSP-RK3 steps."""
+    from paper_1903_04670_amd import dgfs
+    torch = torch_cuda
+    cfg = _couette_small(seed=17)
+    prob, coll = _oracle_rhs(cfg, cfg["F"])
+    pl = gpu_plan(cfg, dg_order=cfg["P"])
+    mesh = dgfs.make_mesh(cfg["K"])
+    F = torch.from_numpy(cfg["F"]).cuda()
+    G = torch.from_numpy(cfg["F"]).cuda()
+    ref = cfg["F"].copy()
+    for k, dt in enumerate([1e-3, 2e-3, 1e-3]):
+        dgfs.step(pl, F, dt, 1, mesh=mesh)
+        torch.cuda.synchronize()
+        ref = odg.ssp_rk3(ref, dt, lambda X: prob.rhs(X, coll))
+        assert rel_linf(F.cpu().numpy(), ref) <= 1e-12, k
+    dgfs.step(pl, G, 1e-3, 1, mesh=mesh)
+    torch.cuda.synchronize()
+    ref_g = odg.ssp_rk3(cfg["F"], 1e-3, lambda X: prob.rhs(X, coll))
+    assert rel_linf(G.cpu().numpy(), ref_g) <= 1e-12
+
+
 def test_ssp_rk3_steps_with_graph_replay(torch_cuda):
     """Three SSP-RK3 steps (one call each, so the captured graph is replayed
     with host work in between), every state checked against the oracle."""
