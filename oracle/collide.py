@@ -1,10 +1,14 @@
 """Collision operator Q^{pq}(f^p, f^q) (oracle; test infrastructure).
 
-``collide`` follows Algorithm 2 of the paper step by step with the oracle's
-own naive DFT; ``collide_direct`` evaluates the projected operator of
-Eq. (apndx_Qprojected) as a direct O(N^6) sum over wave-index pairs, with the
-same quadrature of G^+ (Eqs. realGG, lowrank) and G^- (Eq. Gmm_vss), so the
-two can be compared at small N.  Arrays are indexed [x, y, z].
+``collide`` evaluates the Fourier-Galerkin form of the operator (Sec. 2.1):
+the gain as the low-rank sum of circular convolutions of Eq.
+(apndx_fs_Glm_Qk), with the (rho, sigma) quadrature of Eq. (realGG) as the
+low-rank expansion of G^+, and the loss as one convolution with G^-; each
+convolution goes through the oracle's own naive DFT.  ``collide_direct``
+evaluates the projected operator of Eq. (apndx_Qprojected) as a direct
+O(N^6) sum over wave-index pairs with the same quadrature of G^+ and G^-
+(Eq. Gmm_vss), so the two can be compared at small N.  Arrays are indexed
+[x, y, z].
 """
 import math
 
@@ -75,44 +79,75 @@ def gain_spectra(plan, FTf, FTg):
     return z * FTf, z * FTg
 
 
-def collide(plan, f, g):
-    """Q = beta Re(ifft(QG) - f * ifft(c * FTg)), Algorithm 2.
+def fourier_coefficients(a):
+    """Coefficients a_hat of the truncated Fourier series of the samples a
+    (Sec. 2.1, the series approximating f^p and f^q): the forward DFT over
+    N^3, a_hat = DFT(a) / N^3."""
+    return dft.fft3(a) / a.size
 
-    f = F^p and g = F^q are real N^3 arrays.  The (r, m) loop runs r outer,
-    m inner, in increasing order.  With plan.nyquist_zero, t1 and t2 are
-    formed from the Nyquist-zeroed transforms (gain_spectra)."""
+
+def synthesize(a_hat):
+    """The series sum_k a_hat_k e^{2 pi i k.j/N} evaluated at every grid
+    index j (the inverse of fourier_coefficients)."""
+    return dft.ifft3(a_hat) * a_hat.size
+
+
+def circular_convolution(A, B):
+    """sum over l + m = k (mod N, per axis) of A_l B_m, for every k.
+
+    The Galerkin sum of Eq. (apndx_Qprojected) runs over wave pairs with
+    l + m = k; the modular reading is the one the FFT form of the method
+    computes.  By the convolution theorem the sum equals the coefficients of
+    the pointwise product of the two synthesized series."""
+    return fourier_coefficients(synthesize(A) * synthesize(B))
+
+
+def gain_loss_coefficients(plan, f, g):
+    """(Qhat+, Qhat-): the gain and loss Fourier coefficients of Q^{pq}
+    before the prefactor beta.
+
+    Gain, Eq. (apndx_fs_Glm_Qk) with the low-rank expansion of G+ given by
+    the (rho_r, sigma_m) quadrature of Eq. (realGG):
+        Qhat+_k = sum_{r,m} alpha_rm(k) sum_{l+m'=k} (beta_rm(l) fhat_l)
+                                                    (gamma_rm(m') ghat_m'),
+        alpha_rm(k) = w_r w_m F(k, rho_r, sigma_m)   (table b, Eq. Fkr_vss),
+        beta_rm(l)  = exp(+i pi/L rho_r m_q/(m_p+m_q) l.sigma_m),
+        gamma_rm(m')= exp(-i pi/L rho_r m_p/(m_p+m_q) m'.sigma_m).
+    Loss: Qhat-_k = sum_{l+m'=k} G-(m') fhat_l ghat_m' (table c, Eq. Gmm_vss).
+    The (r, m) sum runs r outer, m inner, in increasing order.  With
+    plan.nyquist_zero the gain convolves the Nyquist-zeroed coefficients
+    (gain_spectra); the loss is unchanged."""
     mp, mq = plan.mp, plan.mq
-    FTf = dft.fft3(f)
-    FTg = dft.fft3(g)
-    Gf, Gg = gain_spectra(plan, FTf, FTg)
-    QG = np.zeros_like(FTf)
+    fh = fourier_coefficients(f)
+    gh = fourier_coefficients(g)
+    fg, gg = gain_spectra(plan, fh, gh)
+    gain = np.zeros_like(fh)
     for r in range(len(plan.rho)):
         for m in range(len(plan.sigma)):
             a = phase_argument(plan, r, m)
-            t1 = np.exp(1j * mq / (mp + mq) * a) * Gf
-            t2 = np.exp(-1j * mp / (mp + mq) * a) * Gg
-            t3 = dft.fft3(dft.ifft3(t1) * dft.ifft3(t2))
-            QG = QG + plan.w_rho[r] * plan.w_sigma[m] * plan.b[r, m] * t3
-    return plan.beta * np.real(dft.ifft3(QG) - f * dft.ifft3(plan.c * FTg))
+            beta_l = np.exp(1j * mq / (mp + mq) * a)
+            gamma_m = np.exp(-1j * mp / (mp + mq) * a)
+            alpha_k = plan.w_rho[r] * plan.w_sigma[m] * plan.b[r, m]
+            gain = gain + alpha_k * circular_convolution(beta_l * fg, gamma_m * gg)
+    loss = circular_convolution(fh, plan.c * gh)
+    return gain, loss
 
 
 def collide_gain_loss(plan, f, g):
-    """The two parts of Algorithm 2 before they are combined:
-    (beta Re ifft(QG), beta Re(f * ifft(c FTg)))."""
-    mp, mq = plan.mp, plan.mq
-    FTf, FTg = dft.fft3(f), dft.fft3(g)
-    Gf, Gg = gain_spectra(plan, FTf, FTg)
-    QG = np.zeros_like(FTf)
-    for r in range(len(plan.rho)):
-        for m in range(len(plan.sigma)):
-            a = phase_argument(plan, r, m)
-            t1 = np.exp(1j * mq / (mp + mq) * a) * Gf
-            t2 = np.exp(-1j * mp / (mp + mq) * a) * Gg
-            QG = QG + plan.w_rho[r] * plan.w_sigma[m] * plan.b[r, m] * \
-                dft.fft3(dft.ifft3(t1) * dft.ifft3(t2))
-    gain = plan.beta * np.real(dft.ifft3(QG))
-    loss = plan.beta * np.real(f * dft.ifft3(plan.c * FTg))
-    return gain, loss
+    """The gain and loss parts of Q^{pq}(f, g) on the grid, each with the
+    prefactor beta: (beta Re gain(c_j), beta Re loss(c_j))."""
+    gain, loss = gain_loss_coefficients(plan, f, g)
+    return plan.beta * np.real(synthesize(gain)), plan.beta * np.real(synthesize(loss))
+
+
+def collide(plan, f, g):
+    """Q^{pq}(f, g) = beta Re sum_k (Qhat+_k - Qhat-_k) e^{i pi/L k.c} on the
+    grid, the operator Algorithm 2 evaluates (the collision step of the
+    fast spectral method, Sec. 2.1).
+
+    f = F^p and g = F^q are real N^3 arrays indexed [x, y, z]."""
+    gain, loss = gain_loss_coefficients(plan, f, g)
+    return plan.beta * np.real(synthesize(gain - loss))
 
 
 def kernel_mode_gain(plan, l, m):

@@ -37,9 +37,15 @@ def moments(Q, N, L, masses):
     return np.tensordot(C, Q, axes=4)
 
 
-def project(Q, N, L, masses):
-    """Q - C^T (C C^T)^{-1} C Q (FP64, dense normal equations)."""
+def project(Q, N, L, masses, rows="all"):
+    """Q - C^T (C C^T)^{-1} C Q (FP64, dense normal equations).  rows="mass"
+    keeps only the mass rows of C (what a single cross-species term
+    Q^{pq} conserves on its own)."""
     C = constraint_rows(N, L, masses)
+    if rows == "mass":
+        C = C[:len(masses)]
+    elif rows != "all":
+        raise ValueError(rows)
     k = C.shape[0]
     Cm = C.reshape(k, -1)
     lam = np.linalg.solve(Cm @ Cm.T, Cm @ Q.ravel())

@@ -67,3 +67,31 @@ class KrookWu:
         f = g * ((1.0 - 3.0 * Qp) + m / K * Qp * v2)
         return f * (-1.5 * dK / K + m * v2 / (2.0 * K * K) * dK) + \
             g * (-3.0 * dQp + m / K * dQp * v2 - m / (K * K) * dK * Qp * v2)
+
+
+def table1_errors(N, Nr, M, ratio, L=12.0, t=5.5, R=None):
+    """(E1, E2): L-infinity errors of the mixture collision term
+    sum_q Q^{pq}(f^p, f^q) against the exact d f^p/dt (the accuracy study
+    of Sec. 3.2, Table 1), for m_1 = 1, m_2 = ratio, on the cell-centred
+    N^3 grid over [-L, L]^3, with N_rho radii and the M-point octahedron
+    (M = 6) or icosahedron (M = 12) set.  The kernel is the constant
+    B_pq = lambda_qp / (4 pi n^q) (gamma = eta = 0).  R: the truncation
+    radius of every pair; None applies the rule of Sec. 2.1 per pair."""
+    from .collide import PairPlan, collide
+    from .quadrature import sphere_set, velocity_grid
+    kw = KrookWu(1.0, ratio)
+    c, _ = velocity_grid(N, L)
+    cx, cy, cz = np.meshgrid(c, c, c, indexing="ij")
+    v2 = cx ** 2 + cy ** 2 + cz ** 2
+    f = {p: kw.f(p, t, v2) for p in (1, 2)}
+    s, w = sphere_set("octahedron" if M == 6 else "icosahedron")
+    masses = {1: 1.0, 2: float(ratio)}
+    errs = []
+    for p in (1, 2):
+        tot = 0.0
+        for q in (1, 2):
+            pl = PairPlan(N, L, masses[p], masses[q], 1.0, 1.0, Nr, s, w, R=R,
+                          beta=kw.beta(p, q), gamma=0.0, eta=0.0)
+            tot = tot + collide(pl, f[p], f[q])
+        errs.append(float(np.max(np.abs(tot - kw.dfdt(p, t, v2)))))
+    return tuple(errs)

@@ -151,10 +151,15 @@ def phi_vss(x, t, eta):
     if eta == 0.0:
         return (4.0 * math.pi * sinc(x)).astype(complex) * np.ones_like(t)
     nmax = _nmax_for(float(np.max(x)) if x.size else 0.0)
-    a = funk_hecke_coeffs(eta, nmax)
     xb, tb = np.broadcast_arrays(x, t)
-    J = spherical_jn_all(nmax, xb)
-    P = legendre_all(nmax, tb)
+    return _funk_hecke_sum(eta, spherical_jn_all(nmax, xb), tb)
+
+
+def _funk_hecke_sum(eta, J, t):
+    """4 pi sum_n a_n (-i)^n j_n(x) P_n(t) with J = [j_0(x) .. j_nmax(x)]."""
+    nmax = J.shape[0] - 1
+    a = funk_hecke_coeffs(eta, nmax)
+    P = legendre_all(nmax, t)
     phase = (-1j) ** np.arange(nmax + 1)
     return 4.0 * math.pi * np.tensordot(a * phase, J * P, axes=(0, 0))
 
@@ -170,9 +175,12 @@ def gain_table(N, L, rho, sigma, mp, mq, gamma, eta):
     safe = np.where(kk == 0.0, 1.0, kk)
     for r, rr in enumerate(rho):
         x = math.pi / L * rr * aq * kk
+        # the Bessel values depend on |k| and r only: computed once per radius
+        J = None if eta == 0.0 else spherical_jn_all(_nmax_for(float(np.max(x))), x)
         for m, s in enumerate(sigma):
             t = np.where(kk == 0.0, 1.0, (s[0] * lx + s[1] * ly + s[2] * lz) / safe)
-            out[r, m] = rr ** (gamma + 2.0) * phi_vss(x, t, eta)
+            phi = phi_vss(x, t, eta) if J is None else _funk_hecke_sum(eta, J, t)
+            out[r, m] = rr ** (gamma + 2.0) * phi
     return out
 
 
