@@ -28,6 +28,9 @@ sys.path.insert(0, HERE)
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
 FP32_PEAK_TFLOPS = 157.3
+# FP32 VALU without packed instructions (which this build does not emit):
+# one FMA per lane per clock, 256 CUs x 64 lanes x 2 flops x 2.4 GHz
+FP32_UNPACKED_TFLOPS = 78.6
 
 
 def parse():
@@ -37,11 +40,12 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--workload", default="couette", choices=["couette", "vjp", "batched", "vss", "table1"],
+    ap.add_argument("--workload", default="couette", choices=["couette", "vjp", "batched", "vss", "table1", "box2d"],
                     help="couette: the headline line (default); vjp: adjoint throughput, 2 species N = 32; "
                          "batched: 1024 uneven instances in one launch per stage vs per-instance launches; "
                          "vss: three-species VSS N = 48, M = 32, N_rho = 24; "
-                         "table1: latency and 64-node throughput at the accuracy study's shapes")
+                         "table1: latency and 64-node throughput at the accuracy study's shapes; "
+                         "box2d: one step of the 2-D box with the three-species VSS N = 48 collision term")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device copy (reference for HBM byte counters)")
     return ap.parse_args()
@@ -93,11 +97,11 @@ TRAFFIC_PROFILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "prof
 KERNEL_SOURCES = ["collide_kernels.hpp", "fft.hpp", "collide.hip"]
 
 
-def measured_path_bytes():
-    """rocprofv3-measured HBM bytes per FP64 evaluation of the whole path
-    (every kernel of a step) from the committed summary, or None when the
-    kernel sources changed since the counters were taken."""
-    return measured_traffic("fp64", key_prefix="path_bytes_per_eval ")
+def measured_path_bytes(prec="fp64"):
+    """rocprofv3-measured HBM bytes per evaluation of the whole path (every
+    kernel of a step, prec "fp64" or "fp32") from the committed summary, or
+    None when the kernel sources changed since the counters were taken."""
+    return measured_traffic(prec, key_prefix="path_bytes_per_eval ")
 
 
 def measured_traffic(kernel, key_prefix="traffic_bytes "):
@@ -151,6 +155,41 @@ def model_bytes_per_eval(N, M, Nr, elt):
     return 2 * (2 * elt) * N ** 3 * M * Nr + 3 * 8 * N ** 3
 
 
+def gain_roofline(cfg, r, tname, elt, steps, evals_per_step, gpp, gpq, gterms, peak_tflops):
+    """Roofline of k_gain_yz for one precision: algorithmic bytes and
+    nominal flops per launch (gain_yz_model x the nodes one launch
+    processes) over the event-timed average launch duration; `bound` is the
+    larger of the HBM and VALU fractions."""
+    name = "k_gain_yz"
+    cnt, tot = r["kern"].get(name, (0, 0.0))
+    if cnt == 0:
+        raise RuntimeError("no gain-kernel launches were recorded")
+    avg_ms = tot / cnt
+    evals_per_launch = evals_per_step / (cnt / steps)
+    nodes_per_launch = evals_per_launch / (cfg["ns"] * cfg["ns"])
+    b, f_term, f_fwd = gain_yz_model(cfg["N"], cfg["M"], cfg["Nrho"], r["sigma_x"], elt, gpp, gpq)
+    bytes_launch = b * nodes_per_launch
+    flops_launch = (f_term * gterms + f_fwd * (gpp + gpq)) * cfg["Nrho"] * nodes_per_launch
+    gbs = bytes_launch / (avg_ms / 1e3) / 1e9
+    tf = flops_launch / (avg_ms / 1e3) / 1e12
+    hbm_frac, alu_frac = gbs / HBM_PEAK_GBS, tf / peak_tflops
+    if hbm_frac >= alu_frac:
+        roof = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(hbm_frac, 4)}
+    else:
+        roof = {"bound": "alu", "achieved": round(tf, 2), "peak": peak_tflops, "unit": "TFLOP/s",
+                "frac": round(alu_frac, 4)}
+    groups = {("double", False): max(1, 128 // (2 * cfg["N"])), ("float", False): 1}
+    kname = "%s<%s, %d, %d, %d, false>" % (name, tname, cfg["N"], groups[(tname, False)], 1 if elt == 8 else 2)
+    roof.update({"traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+                 "traffic": measured_traffic(kname), "kernel": kname, "avg_launch_ms": round(avg_ms, 4),
+                 "evals_per_launch": evals_per_launch, "gain_slots_per_node": gpp + gpq,
+                 "direction_terms_per_node": gterms, "algorithmic_bytes_per_launch": bytes_launch,
+                 "nominal_flops_per_launch": flops_launch, "hbm_GBps": round(gbs, 1),
+                 "hbm_frac": round(hbm_frac, 4), "fp_tflops": round(tf, 2), "alu_frac": round(alu_frac, 4)})
+    return roof
+
+
 def run(args):
     import torch
     from paper_1903_04670_amd import dgfs, workloads as wl
@@ -202,33 +241,70 @@ def run(args):
     return cfg, evals_per_step, out
 
 
-def cpu_baseline(seconds):
-    """The oracle (as it stands) on the host: one ordered-pair evaluation at
-    a time on the same N = 32 workload until about `seconds` have passed."""
-    from threadpoolctl import threadpool_info
-    from oracle.collide import PairPlan, collide
-    from oracle.quadrature import sphere_set
-    from paper_1903_04670_amd import workloads as wl
-    cfg = wl.couette_two_species(K=1, P=1)
-    s, w = sphere_set(cfg["sphere"], cfg["M"])
-    plans = {(p, q): PairPlan(cfg["N"], cfg["L"], cfg["masses"][p], cfg["masses"][q], cfg["omega"][p][q],
-                              cfg["alpha"][p][q], cfg["Nrho"], s, w, R=cfg["R"][p][q])
-             for p in range(2) for q in range(2)}
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _time_oracle(plans, F, seconds, min_evals):
+    """Ordered-pair evaluations of the oracle, cycling over nodes and pairs,
+    until `seconds` have passed and at least `min_evals` were done."""
+    from oracle.collide import collide
+    pairs = list(plans)
     n = 0
     t0 = time.perf_counter()
-    pairs = list(plans)
     while True:
-        node = n // 4 % cfg["F"].shape[0]
-        p, q = pairs[n % 4]
-        collide(plans[p, q], cfg["F"][node, p], cfg["F"][node, q])
+        node = n // len(pairs) % F.shape[0]
+        p, q = pairs[n % len(pairs)]
+        collide(plans[p, q], F[node, p], F[node, q])
         n += 1
-        if time.perf_counter() - t0 > seconds and n >= 4:
+        if time.perf_counter() - t0 > seconds and n >= min_evals:
             break
-    dt = time.perf_counter() - t0
+    return n, time.perf_counter() - t0
+
+
+def cpu_baseline(seconds):
+    """The oracle (as it stands) on the host's cores: ordered-pair
+    evaluations of the Couette workload (N = 32, M = 12, N_rho = 16) for
+    about `seconds` (the reported value), plus at least 3 evaluations of the
+    space-homogeneous shape (N = 16, octahedron, N_rho = 8) and one of the
+    precision workload's shape (N = 48, Fibonacci M = 32, N_rho = 24).  Plan
+    tables (Algorithm 1) are built outside the timed regions; for the N = 48
+    shape the table is built with alpha = 1, because the oracle's VSS
+    Funk-Hecke table takes minutes at N_rho = 24 and the evaluation's
+    arithmetic does not depend on the table's values."""
+    from threadpoolctl import threadpool_info
+    from oracle.collide import PairPlan
+    from oracle.quadrature import sphere_set
+    from paper_1903_04670_amd import workloads as wl
+
+    def pair_plans(cfg, pairs, alpha=None):
+        s, w = sphere_set(cfg["sphere"], cfg["M"])
+        return {(p, q): PairPlan(cfg["N"], cfg["L"], cfg["masses"][p], cfg["masses"][q], cfg["omega"][p][q],
+                                 cfg["alpha"][p][q] if alpha is None else alpha, cfg["Nrho"], s, w,
+                                 R=cfg["R"][p][q]) for p, q in pairs}
+    cfg2 = wl.couette_two_species(K=1, P=1)
+    n2, t2 = _time_oracle(pair_plans(cfg2, [(p, q) for p in range(2) for q in range(2)]), cfg2["F"], seconds, 4)
+    cfg1 = wl.homogeneous_single()
+    n1, t1 = _time_oracle(pair_plans(cfg1, [(0, 0)]), cfg1["F"], 0.0, 3)
+    cfg5 = wl.precision_vss(n_nodes=1)
+    n5, t5 = _time_oracle(pair_plans(cfg5, [(0, 2)], alpha=1.0), cfg5["F"], 0.0, 1)
     threads = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
-    return dict(value=n / dt, unit="collision evals/s", cores=int(threads), kind="oracle",
+    return dict(value=n2 / t2, unit="collision evals/s", cores=int(threads), kind="oracle",
                 sample="%d ordered-pair evaluations (N=32, M=12, N_rho=16) of the Couette workload, %.1f s"
-                       % (n, dt))
+                       % (n2, t2),
+                cpu_model=_cpu_model(), affinity_cores=len(os.sched_getaffinity(0)),
+                other_shapes=[
+                    {"shape": "N=16, octahedron M=6, N_rho=8 (space-homogeneous)", "evals": n1,
+                     "seconds": round(t1, 3), "evals_per_s": round(n1 / t1, 3)},
+                    {"shape": "N=48, Fibonacci M=32, N_rho=24, pair (1, 4) masses (precision workload)",
+                     "evals": n5, "seconds": round(t5, 3), "evals_per_s": round(n5 / t5, 4)}])
 
 
 def _time_cuda(fn, steps, warmup):
@@ -348,6 +424,42 @@ def bench_vss(args):
             "data": "synthetic", "config": {"workload": cfg["name"], "nodes": 4, "pairs": 9}}
 
 
+def bench_box2d(args):
+    """The precision workload's 2-D shape: 16 x 8 elements with P = 1 (512
+    nodes) on the unit square, four diffuse walls, three species (masses 1,
+    2, 4), VSS alpha = 1.4, N = 48, Fibonacci M = 32, N_rho = 24.  One
+    forward-Euler step (the 2-D transport plus 512 x 9 collision
+    evaluations) in FP32-mixed with the FP64 projection and in FP64."""
+    import torch
+    from paper_1903_04670_amd import dgfs, workloads as wl
+    cfg = wl.precision_vss(n_nodes=512)
+    F0 = torch.from_numpy(cfg["F"]).cuda()
+    del cfg["F"]
+    walls = {"left": ((0.0, -0.3, 0.0), 1.0), "right": ((0.0, 0.3, 0.0), 1.0),
+             "bottom": ((0.2, 0.0, 0.0), 1.0), "top": ((-0.2, 0.0, 0.0), 1.0)}
+    mesh = dgfs.make_mesh2d(16, 8, periodic=(False, False), walls=walls)
+    res, kern = {}, {}
+    for prec in ("fp32", "fp64"):
+        plan = dgfs.Plan(cfg["masses"], cfg["omega"], cfg["alpha"], cfg["N"], cfg["L"], cfg["Nrho"],
+                         sphere=cfg["sphere"], M=cfg["M"], R=cfg["R"], dg_order=1, precision=prec)
+        ws = dgfs.workspace(plan, 512, dgfs.OP_STEP)
+        F = F0.clone()
+        project = prec == "fp32"
+        t = _time_cuda(lambda: dgfs.step_2d(plan, F, 1e-4, mesh, project=project, euler=True, ws=ws), 1, 1)
+        res[prec] = 512 * 9 / t
+        dgfs.profile_enable(True)
+        dgfs.step_2d(plan, F, 1e-4, mesh, project=project, euler=True, ws=ws)
+        torch.cuda.synchronize()
+        kern[prec] = {k: round(v[1], 3) for k, v in sorted(dgfs.profile_read().items())}
+        dgfs.profile_enable(False)
+        del plan, ws, F
+        torch.cuda.empty_cache()
+    return {"metric": "collision evals/s in a 2-D box step, 3-species VSS N=48^3 M=32 N_rho=24, 512 nodes",
+            "value": round(res["fp64"], 1), "unit": "collision evals/s", "fp32_mixed": round(res["fp32"], 1),
+            "kernels_ms_per_step": kern, "n_gpus": 1, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": "2-D box 16x8 elements P=1, " + cfg["name"], "nodes": 512, "pairs": 9}}
+
+
 # Table 1 cells whose P100 FP64 time per evaluation the paper prints
 # (Sec. 3.2, Table 1): (N, N_rho, M, seconds).  Context only.
 TABLE1_TIMES = [(16, 8, 6, 0.00056), (16, 8, 12, 0.00085), (24, 6, 12, 0.00114), (32, 8, 12, 0.00287),
@@ -394,7 +506,8 @@ def main():
         if args.gpus != 1:
             print("bench.py measures one GPU only.", file=sys.stderr)
             sys.exit(2)
-        fn = {"vjp": bench_vjp, "batched": bench_batched, "vss": bench_vss, "table1": bench_table1}[args.workload]
+        fn = {"vjp": bench_vjp, "batched": bench_batched, "vss": bench_vss, "table1": bench_table1,
+              "box2d": bench_box2d}[args.workload]
         print(json.dumps(fn(args)), flush=True)
         return
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -406,41 +519,17 @@ def main():
     r64, r32 = res["fp64"], res["fp32"]
     n64, n32 = res["fp64_nyq"], res["fp32_nyq"]
     value = evals_per_step / (r64["ms"] / 1e3)
-    # dominant kernel roofline (FP64 path)
-    name = "k_gain_yz"
-    cnt, tot = r64["kern"].get(name, (0, 0.0))
-    if cnt == 0:
-        raise RuntimeError("no gain-kernel launches were recorded")
-    avg_ms = tot / max(cnt, 1)
-    launches_per_step = cnt / args.steps
-    evals_per_launch = evals_per_step / max(launches_per_step, 1)
-    npairs = cfg["ns"] * cfg["ns"]
-    nodes_per_launch = evals_per_launch / npairs
     gpp, gpq, gterms = gain_schedule(cfg)
-    b, f_term, f_fwd = gain_yz_model(cfg["N"], cfg["M"], cfg["Nrho"], r64["sigma_x"], 8, gpp, gpq)
-    bytes_launch = b * nodes_per_launch
-    flops_launch = (f_term * gterms + f_fwd * (gpp + gpq)) * cfg["Nrho"] * nodes_per_launch
-    achieved_gbs = bytes_launch / (avg_ms / 1e3) / 1e9
-    achieved_tf = flops_launch / (avg_ms / 1e3) / 1e12
-    hbm_frac = achieved_gbs / HBM_PEAK_GBS
-    alu_frac = achieved_tf / FP64_PEAK_TFLOPS
-    if hbm_frac >= alu_frac:
-        roof = {"bound": "hbm", "achieved": round(achieved_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(hbm_frac, 4)}
-    else:
-        roof = {"bound": "alu", "achieved": round(achieved_tf, 2), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(alu_frac, 4)}
-    roof.update({"traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
-                 "traffic": measured_traffic("%s<double, %d, %d, 1, false>"
-                                             % (name, cfg["N"], max(1, 128 // (2 * cfg["N"])))),
-                 "kernel": name,
-                 "avg_launch_ms": round(avg_ms, 4),
-                 "evals_per_launch": evals_per_launch, "gain_slots_per_node": gpp + gpq,
-                 "direction_terms_per_node": gterms, "algorithmic_bytes_per_launch": bytes_launch,
-                 "nominal_flops_per_launch": flops_launch,
-                 "hbm_GBps": round(achieved_gbs, 1),
-                 "hbm_frac": round(hbm_frac, 4), "fp64_tflops": round(achieved_tf, 2),
-                 "fp64_alu_frac": round(alu_frac, 4)})
+    roof = gain_roofline(cfg, r64, "double", 8, args.steps, evals_per_step, gpp, gpq, gterms, FP64_PEAK_TFLOPS)
+    roof32 = gain_roofline(cfg, r32, "float", 4, args.steps, evals_per_step, gpp, gpq, gterms, FP32_PEAK_TFLOPS)
+    roof32["issue_ceiling_tflops"] = FP32_UNPACKED_TFLOPS
+    roof32["issue_ceiling_frac"] = round(roof32["fp_tflops"] / FP32_UNPACKED_TFLOPS, 4)
+    value32 = evals_per_step / (r32["ms"] / 1e3)
+    path = {}
+    for prec, v in (("fp64", value), ("fp32", value32)):
+        b = measured_path_bytes(prec)
+        path[prec] = None if b is None else {"bytes_per_eval": b, "GBps": round(v * b / 1e9, 1),
+                                             "frac": round(v * b / (HBM_PEAK_GBS * 1e9), 4)}
     line = {
         "metric": "collision evals/s at N=32^3 (FP64; FP32-mixed beside it)",
         "value": round(value, 1),
@@ -456,25 +545,29 @@ def main():
         "data": "synthetic",
         "config": {"workload": "couette 2 species N=32 M=12 Nrho=16 K=16 P=3 (64 nodes), SSP-RK3 step",
                    "evals_per_step": evals_per_step, "nodes": 64, "pairs": 4},
-        "fp32_mixed": {"value": round(evals_per_step / (r32["ms"] / 1e3), 1), "ms_per_step": round(r32["ms"], 3),
+        "fp32_mixed": {"value": round(value32, 1), "ms_per_step": round(r32["ms"], 3),
                        "projection": "fp64", "dtype": "f32 transforms, f64 moments/projection"},
         "graph_replay": {"fp64_evals_per_s": round(evals_per_step / (r64["ms_graph"] / 1e3), 1),
                          "fp32_mixed_evals_per_s": round(evals_per_step / (r32["ms_graph"] / 1e3), 1)},
         "kernels_ms_per_step": {k: round(v[1] / args.steps, 4) for k, v in sorted(r64["kern"].items())},
         "kernels_ms_per_step_fp32": {k: round(v[1] / args.steps, 4) for k, v in sorted(r32["kern"].items())},
         "roofline": roof,
-        "model_roofline": {
-            "what": "evals/s x model bytes per eval / 8 TB/s (whole path)",
+        "roofline_fp32_mixed": roof32,
+        "path_hbm": {
+            "what": "whole path (every kernel of a step): rocprofv3-measured HBM bytes per evaluation "
+                    "(FETCH_SIZE + WRITE_SIZE, copy-calibrated) x evals/s, against 8 TB/s; null when the "
+                    "kernels changed since the counters were taken",
+            "fp64": path["fp64"], "fp32_mixed": path["fp32"]},
+        "model_equivalent": {
+            "what": "not a roofline fraction: the HBM rate the survey's cost model (one HBM round trip of an "
+                    "N^3 complex intermediate per (r, m) term plus three real N^3 arrays) would need for the "
+                    "measured evals/s; this design moves fewer bytes (sum over m before the forward transform, "
+                    "shared x-shifted arrays, reused gain sums), see path_hbm",
             "bytes_per_eval_fp64": model_bytes_per_eval(cfg["N"], cfg["M"], cfg["Nrho"], 8),
             "bytes_per_eval_fp32_mixed": model_bytes_per_eval(cfg["N"], cfg["M"], cfg["Nrho"], 4),
-            "fp64_frac": round(value * model_bytes_per_eval(cfg["N"], cfg["M"], cfg["Nrho"], 8)
-                               / (HBM_PEAK_GBS * 1e9), 4),
-            "fp32_mixed_frac": round(evals_per_step / (r32["ms"] / 1e3)
-                                     * model_bytes_per_eval(cfg["N"], cfg["M"], cfg["Nrho"], 4)
-                                     / (HBM_PEAK_GBS * 1e9), 4),
-            "measured_bytes_per_eval_fp64": measured_path_bytes(),
-            "measured_path_GBps_fp64": (None if measured_path_bytes() is None
-                                        else round(value * measured_path_bytes() / 1e9, 1))},
+            "fp64_TBps": round(value * model_bytes_per_eval(cfg["N"], cfg["M"], cfg["Nrho"], 8) / 1e12, 3),
+            "fp32_mixed_TBps": round(value32 * model_bytes_per_eval(cfg["N"], cfg["M"], cfg["Nrho"], 4) / 1e12,
+                                     3)},
         "nyquist_zero": {
             "what": "variant operator, not the headline: the gain's translates drop the Nyquist planes of "
                     "fft(f), so u1, u2 are real and one complex transform gives both (real-packed k_gain_yz)",
@@ -483,8 +576,8 @@ def main():
             "graph_replay": {"fp64_evals_per_s": round(evals_per_step / (n64["ms_graph"] / 1e3), 1),
                              "fp32_mixed_evals_per_s": round(evals_per_step / (n32["ms_graph"] / 1e3), 1)},
             "k_gain_yz_avg_launch_ms": {
-                "fp64": round(n64["kern"][name][1] / max(n64["kern"][name][0], 1), 4),
-                "fp32_mixed": round(n32["kern"][name][1] / max(n32["kern"][name][0], 1), 4)},
+                "fp64": round(n64["kern"]["k_gain_yz"][1] / max(n64["kern"]["k_gain_yz"][0], 1), 4),
+                "fp32_mixed": round(n32["kern"]["k_gain_yz"][1] / max(n32["kern"]["k_gain_yz"][0], 1), 4)},
             "kernels_ms_per_step": {k: round(v[1] / args.steps, 4) for k, v in sorted(n64["kern"].items())},
             "kernels_ms_per_step_fp32": {k: round(v[1] / args.steps, 4) for k, v in sorted(n32["kern"].items())}},
         "finite": all(r["finite"] for r in res.values()),

@@ -20,15 +20,32 @@
  *     [x][y][z] with z fastest, velocity c_j = -L + (j + 1/2) h, h = 2L/N.
  *   - `stream` is a hipStream_t (NULL = the null stream).  Calls are stream
  *     ordered and asynchronous: they neither allocate device memory nor
- *     synchronise the host (except dgfs_plan_create/destroy).
+ *     synchronise the host, with these exceptions:
+ *       * dgfs_plan_create / dgfs_plan_destroy allocate and free the plan's
+ *         tables and synchronise (destroy first waits for queued replays of
+ *         the plan's captured step);
+ *       * DGFS_CHECK allocates a 4-byte counter (stream-ordered
+ *         hipMallocAsync) and synchronises the stream to read it;
+ *       * dgfs_step, when its key (mesh, n_nodes, F, dt, flags, workspace,
+ *         chunk width) differs from the captured one (always on the first
+ *         call for a plan), creates a private capture stream and an event,
+ *         captures and instantiates a HIP graph, and first waits on the host
+ *         for the earlier graph's queued replays;
+ *       * dgfs_collide_batched stages its item descriptors in a pinned host
+ *         buffer (hipHostMalloc when a larger one is needed), waits on the
+ *         host for the previous call's copy from that buffer, and serialises
+ *         concurrent callers on a process-wide lock;
+ *       * dgfs_autotune synchronises the stream and creates timing events;
+ *       * while dgfs_profile_enable is on, every launch creates two events.
  *   - `ws` / `ws_bytes`: caller-owned device workspace of at least
  *     dgfs_workspace_bytes(plan, n_nodes, op) bytes, 256-byte aligned.
  *   - Validation errors are returned before anything is launched.  A HIP
  *     launch error is returned as DGFS_EHIP.  Nothing throws across the ABI;
  *     dgfs_last_error() gives a thread-local message for the last non-OK
  *     status.
- *   - A plan is immutable after creation and may be used concurrently on
- *     different streams with distinct workspaces.
+ *   - A plan is immutable after creation, except that dgfs_autotune stores
+ *     the chunk width it picks in it, and may be used concurrently on
+ *     different streams with distinct workspaces (dgfs_autotune excepted).
  */
 #ifndef DGFS_H
 #define DGFS_H
@@ -138,7 +155,15 @@ size_t dgfs_workspace_bytes(dgfs_plan plan, int64_t n_nodes, int32_t op);
  *                                     * ifft(e^{-i m_p/(m_p+m_q) a} fft f^q) ).
  *   fp, fq     device, node n block at fp + n*node_stride (N^3 doubles each)
  *   Q          device, node n block at Q + n*out_stride
- *   flags      DGFS_ACCUMULATE, DGFS_CHECK
+ *   flags      DGFS_ACCUMULATE, DGFS_PROJECT, DGFS_CHECK
+ * DGFS_PROJECT replaces each node's Q by its FP64 least-squares projection
+ * Q - C^T (C C^T)^{-1} C Q onto the invariants this single term conserves
+ * (Sec. 2: collisions conserve the mass of each species and the total
+ * momentum and energy).  Q^{pq} alone conserves the mass of species p, the
+ * one row of C (weight h^3).  The self-collision term of one distribution
+ * (p == q and fp == fq, the same pointer) also conserves momentum and
+ * energy: rows m_p c_d h^3 (d = x, y, z) and m_p |c|^2/2 h^3.  With
+ * DGFS_ACCUMULATE the projected term is added into Q.
  */
 dgfs_status dgfs_collide(dgfs_plan plan, int64_t n_nodes, int32_t p, int32_t q,
                          const double *fp, const double *fq, int64_t node_stride,
@@ -203,6 +228,46 @@ dgfs_status dgfs_step(dgfs_plan plan, const dgfs_mesh *mesh, int64_t n_nodes,
                       void *ws, size_t ws_bytes, void *stream);
 
 /*
+ * Two-dimensional (x, y) physical mesh for the DG transport term: the
+ * extension to higher spatial dimensions that Sec. 3.3 leaves to future
+ * work (its footnote).  Host struct.
+ *   Kx, Ky       elements in x and y: uniform rectangles on
+ *                [x_left, x_right] x [y_bottom, y_top]
+ *   periodic_x   1: periodic in x (the left/right wall fields are unused);
+ *                0: purely diffuse (Maxwell) walls at x_left and x_right
+ *   periodic_y   the same for y and the bottom/top walls
+ *   u_*[3], T_*  wall velocity and temperature of each side; the wall
+ *                density of every boundary node is fixed each stage by zero
+ *                net mass flux through that node
+ * Tensor-product Gauss-Lobatto nodes, (P+1)^2 per element (P = the plan's
+ * dg_order, 1 <= P <= 4), upwind flux on every face.  Node order:
+ *   node = ((ey*Kx + ex)*(P+1) + j)*(P+1) + i,  i along x, j along y.
+ * The boundary nodes of all walls and species must number at most 8192
+ * (2 (Kx + Ky) (P+1) ns <= 8192).
+ */
+typedef struct {
+  int32_t Kx, Ky;
+  double x_left, x_right, y_bottom, y_top;
+  int32_t periodic_x, periodic_y;
+  double u_left[3], T_left;
+  double u_right[3], T_right;
+  double u_bottom[3], T_bottom;
+  double u_top[3], T_top;
+} dgfs_mesh2d;
+
+/*
+ * dgfs_rhs and dgfs_step on a 2-D mesh: dF^p/dt = -(c_x dF^p/dx + c_y
+ * dF^p/dy) + sum_q Q^{pq}(F^p, F^q), the collision term as in dgfs_rhs
+ * (flags DGFS_PROJECT and DGFS_CHECK; DGFS_EULER for the step).  n_nodes
+ * must equal Kx*Ky*(P+1)^2; F and dFdt are [node][species][N^3]; the
+ * workspace is that of DGFS_OP_RHS / DGFS_OP_STEP for n_nodes.
+ */
+dgfs_status dgfs_rhs_2d(dgfs_plan plan, const dgfs_mesh2d *mesh, int64_t n_nodes, const double *F,
+                        double *dFdt, uint32_t flags, void *ws, size_t ws_bytes, void *stream);
+dgfs_status dgfs_step_2d(dgfs_plan plan, const dgfs_mesh2d *mesh, int64_t n_nodes, double *F, double dt,
+                         int32_t n_steps, uint32_t flags, void *ws, size_t ws_bytes, void *stream);
+
+/*
  * Heterogeneous batch: items of different plans (different N, species,
  * quadratures) evaluated by one launch per pipeline stage.
  *   plans[n_plans]  host array of plans
@@ -243,10 +308,15 @@ dgfs_status dgfs_profile_enable(int32_t on);
 int32_t dgfs_profile_read(int32_t cap, char *names, int64_t *counts, double *total_ms);
 
 /*
- * Launch-schedule autotuning.  Times dgfs_collide on the given inputs for the
- * candidate chunk widths (evaluations per launch: 8 .. 256, those whose
- * workspace fits in ws_bytes) and keeps the fastest in the plan; `chosen`
- * (host, may be NULL) receives it.  The choice is appended to a text cache
+ * Launch-schedule autotuning.  Times dgfs_collide on the given inputs over
+ * three schedule dimensions, none of which changes a result bit: the chunk
+ * width (evaluations per launch: 8 .. 256, those whose workspace fits in
+ * ws_bytes), then at the best width the number of blocks splitting each
+ * x-line set's (r, sigma_x) loop in the x-shift stage (1, 2, 4, 8), then
+ * whether the x stage of the gain serves a mirrored pair slot in the same
+ * pass.  The fastest schedule is kept in the plan; `chosen` (host int32[3],
+ * may be NULL) receives (width, split, fusion), split 0 and fusion -1
+ * meaning the default was fastest.  The choice is appended to a text cache
  * (path $DGFS_TUNE_CACHE, default ~/.cache/dgfs_tune.txt) keyed by GPU
  * architecture and plan shape, and dgfs_plan_create reads it unless
  * DGFS_NO_TUNE_CACHE is set.  Synchronises the stream; overwrites Q; must

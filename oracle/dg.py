@@ -138,3 +138,90 @@ def ssp_rk3(F, dt, rhs):
     F1 = F + dt * rhs(F)
     F2 = 0.75 * F + 0.25 * (F1 + dt * rhs(F1))
     return F / 3.0 + 2.0 / 3.0 * (F2 + dt * rhs(F2))
+
+
+class Box2D:
+    """Transport part in two space dimensions, x and y: the extension of the
+    1-D-x scheme above that Sec. 3.3 leaves to future work (its footnote on
+    higher spatial dimensions).  Kx x Ky uniform rectangles on
+    [x0, x1] x [y0, y1], tensor-product GLL nodes ((P+1)^2 per element),
+    upwind flux on every face.  Each direction is periodic or bounded by two
+    Maxwell diffuse walls (walls = {"left": (u_w, T_w), "right": ..,
+    "bottom": .., "top": ..}).
+
+    With the exact mass matrices of the tensor basis, the strong form
+    separates: the right-hand side is the 1-D operator of advect_rhs along
+    every x-line of nodes (fixed element row and local j) with velocity c_x,
+    plus the same along every y-line with c_y.  A diffuse-wall node emits
+    n_w M_w on its inflow half with n_w from zero net mass flux through that
+    node.
+
+    Layout of F: [node, species, N, N, N],
+    node = ((ey Kx + ex)(P+1) + j)(P+1) + i, i along x and j along y."""
+
+    def __init__(self, N, L, masses, Kx, Ky, P, extent=((0.0, 1.0), (0.0, 1.0)),
+                 periodic=(False, True), walls=None):
+        self.N, self.L, self.masses = N, L, list(masses)
+        self.Kx, self.Ky, self.P = Kx, Ky, P
+        (self.x0, self.x1), (self.y0, self.y1) = extent
+        self.hx, self.hy = (self.x1 - self.x0) / Kx, (self.y1 - self.y0) / Ky
+        self.periodic = tuple(bool(v) for v in periodic)
+        self.r, self.Minv, self.Dr = dg_operators(P)
+        c, _ = velocity_grid(N, L)
+        cx, cy, _ = np.meshgrid(c, c, c, indexing="ij")
+        self.cx, self.cy = cx, cy
+        walls = walls or {}
+        self.Mw = {side: [wall_maxwellian(N, L, m, uw, Tw) for m in masses]
+                   for side, (uw, Tw) in walls.items()}
+        for side, per in (("left", 0), ("right", 0), ("bottom", 1), ("top", 1)):
+            if not self.periodic[per] and side not in self.Mw:
+                raise ValueError("no wall given for the %s side" % side)
+
+    def n_nodes(self):
+        return self.Kx * self.Ky * (self.P + 1) ** 2
+
+    def node_xy(self):
+        """(x, y) of every node in node order."""
+        r = self.r
+        out = np.zeros((self.Ky, self.Kx, self.P + 1, self.P + 1, 2))
+        for ey in range(self.Ky):
+            for ex in range(self.Kx):
+                xs = self.x0 + (ex + 0.5 * (r + 1.0)) * self.hx
+                ys = self.y0 + (ey + 0.5 * (r + 1.0)) * self.hy
+                out[ey, ex, :, :, 0] = xs[None, :]
+                out[ey, ex, :, :, 1] = ys[:, None]
+        return out.reshape(-1, 2)
+
+    def _line(self, u, c, h, periodic, Mw_lo, Mw_hi):
+        """advect_rhs along one line u [K, P+1, N, N, N] with velocity c;
+        ghosts from periodicity or the two diffuse walls."""
+        if periodic:
+            gl, gr = u[-1, -1], u[0, 0]
+        else:
+            gl = diffuse_ghost(u[0, 0], c, Mw_lo, True)
+            gr = diffuse_ghost(u[-1, -1], c, Mw_hi, False)
+        return advect_rhs(u, c, h, self.Minv, self.Dr, gl, gr)
+
+    def transport_rhs(self, F):
+        Kx, Ky, Pp1, N = self.Kx, self.Ky, self.P + 1, self.N
+        ns = len(self.masses)
+        U = F.reshape(Ky, Kx, Pp1, Pp1, ns, N, N, N)
+        out = np.zeros_like(U)
+        for p in range(ns):
+            ml, mr = self.Mw.get("left", [None] * ns)[p], self.Mw.get("right", [None] * ns)[p]
+            mb, mt = self.Mw.get("bottom", [None] * ns)[p], self.Mw.get("top", [None] * ns)[p]
+            for ey in range(Ky):
+                for j in range(Pp1):
+                    u = U[ey, :, j, :, p]                        # [Kx, P+1 (i), ...]
+                    out[ey, :, j, :, p] += self._line(u, self.cx, self.hx, self.periodic[0], ml, mr)
+            for ex in range(Kx):
+                for i in range(Pp1):
+                    u = U[:, ex, :, i, p]                        # [Ky, P+1 (j), ...]
+                    out[:, ex, :, i, p] += self._line(u, self.cy, self.hy, self.periodic[1], mb, mt)
+        return out.reshape(F.shape)
+
+    def rhs(self, F, collision=None):
+        out = self.transport_rhs(F)
+        if collision is not None:
+            out = out + collision(F)
+        return out

@@ -159,6 +159,31 @@ template <int N> __device__ __forceinline__ void group_sync() {
   }
 }
 
+// Column phases of a lane pair (c, p) holding rows y = 2n + p, FP64, by
+// recurrence instead of one table read per row: the wave index of row y is
+// v = y below N/2 and y - N from N/2 on, so consecutive rows of a lane
+// differ by e^{2 i beta} = ph(2) within each half.  Rows 2n + p, n < N/4,
+// get zph ph(1)^p ph(2)^n; the upper half restarts from the table at rows
+// N/2 + p and N/2 + 2 + p (the first may be a zeroed Nyquist entry, which
+// the second skips) and steps by ph(2).  Four staged values per side
+// replace 16 per-lane table reads, each an LDS round trip the next
+// multiply waits for; the recurrence adds rounding of a few ulp.
+// Requires N % 4 == 0 and N >= 8 (ph(2) is not a Nyquist entry).
+template <typename T, int N>
+__device__ __forceinline__ void col_phases_rec(cplx<T> (&h)[N / 2], const cplx<T> *ph, cplx<T> zph, int p) {
+  constexpr int Q = N / 4;
+  const cplx<T> rho = ph[2];
+  const cplx<T> z1 = cmul(zph, ph[1]);
+  cplx<T> phi{p ? z1.x : zph.x, p ? z1.y : zph.y};
+#pragma unroll
+  for (int n = 0; n < N / 2; ++n) {
+    if (n == Q) phi = cmul(zph, ph[N / 2 + p]);
+    else if (n == Q + 1) phi = cmul(zph, ph[N / 2 + 2 + p]);
+    else if (n > 0) phi = cmul(phi, rho);
+    h[n] = cmul(h[n], phi);
+  }
+}
+
 // Compensated accumulation (used by the FP32 path): Kahan's summation with
 // the correction kept so that s + c is the running sum.  The rounding error
 // of each addition, y - (t - s), is recovered exactly and fed into the next
@@ -355,11 +380,16 @@ __device__ __forceinline__ void gain_yz_body(const PipeArgs &a, int jx, int r, i
     pf0 = gload(pyz + ((size_t)r * a.M + m) * 2 * N, l);
     pf1 = gload(pyz + (((size_t)a.Nr + r) * a.M + m) * 2 * N, l);
   };
+  constexpr bool kRec = sizeof(T) == 8 && N % 4 == 0 && N >= 8 && !PACK;
   auto finish_col = [&](int side, int m, C<T>(&h)[H], C<T>(*buf)[N + 1]) {
     const C<T> *ph = phs + side * 2 * N;
     const C<T> zph = ph[N + c];
+    if constexpr (kRec) {
+      col_phases_rec<T, N>(h, ph, zph, p);
+    } else {
 #pragma unroll
-    for (int n = 0; n < H; ++n) h[n] = cmul(h[n], cmul(ph[2 * n + p], zph));
+      for (int n = 0; n < H; ++n) h[n] = cmul(h[n], cmul(ph[2 * n + p], zph));
+    }
     fft_pair<N, +1>(h, p);
 #pragma unroll
     for (int k = 0; k < H; ++k) buf[p * H + k][c] = h[k];
@@ -547,25 +577,26 @@ __device__ __forceinline__ void gain_yz_body(const PipeArgs &a, int jx, int r, i
       }
       group_sync<N>();
     } else {
-      auto do_side = [&](int side) {
-        if (active) col_pass(side, m, s, lds[g]);
-        group_sync<N>();
-        if (active) {
-          C<T> h[H];
+      // side 0's row pass transforms in u1 itself (no copy); side 1's
+      // result goes straight into the product
+      if (active) col_pass(0, m, s, lds[g]);
+      group_sync<N>();
+      if (active) {
 #pragma unroll
-          for (int n = 0; n < H; ++n) h[n] = lds[g][c][2 * n + p];
-          fft_pair<N, +1>(h, p);
-          if (side == 0) {
+        for (int n = 0; n < H; ++n) u1[n] = lds[g][c][2 * n + p];
+        fft_pair<N, +1>(u1, p);
+      }
+      group_sync<N>();
+      if (active) col_pass(1, m, s, lds[g]);
+      group_sync<N>();
+      if (active) {
+        C<T> h[H];
 #pragma unroll
-            for (int k = 0; k < H; ++k) u1[k] = h[k];
-          } else {
-            accumulate(h);
-          }
-        }
-        group_sync<N>();
-      };
-      do_side(0);
-      do_side(1);
+        for (int n = 0; n < H; ++n) h[n] = lds[g][c][2 * n + p];
+        fft_pair<N, +1>(h, p);
+        accumulate(h);
+      }
+      group_sync<N>();
     }
   }
   }

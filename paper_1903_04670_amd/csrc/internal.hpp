@@ -43,6 +43,10 @@ struct dgfs_plan_s {
   bool nyquist_zero = false;  // gain translates drop the Nyquist planes (real-packed VHS gain)
   bool vhs = true;      // every pair has alpha == 1 (sigma-independent gain table)
   int chunk_evals = 0;  // evaluations per launch chosen by dgfs_autotune or its cache (0 = default)
+  // launch schedule knobs that dgfs_autotune also picks (0 / -1 = default);
+  // neither changes a result bit
+  int shift_split = 0;   // k_shift_x blocks per x-line set: 1, 2, 4 or 8
+  int gain_x_fuse = -1;  // k_gain_x serves a mirrored slot in the same pass: 0 or 1
   void *vss_dev = nullptr;  // VSS gain tables of all pairs (separate allocation)
   // device memory owned by the plan
   void *dev = nullptr;
@@ -75,6 +79,8 @@ struct dgfs_plan_s {
   std::vector<double> dg_r, dg_Dr, dg_Minv;
   // (C C^T)^{-1} of the conservation constraints of all species (ns+4)^2
   std::vector<double> proj_ginv;
+  // the same for each species alone, (1+4)^2 per species
+  std::vector<std::vector<double>> proj_ginv_self;
   // graph cache of dgfs_step (guarded by graph_mu)
   void *graph_cache = nullptr;
   // host copies for dgfs_plan_table

@@ -281,6 +281,14 @@ extern "C" dgfs_status dgfs_plan_create(const dgfs_params *prm, dgfs_plan *out) 
       delete pl;
       return DGFS_EINVAL;
     }
+    // one species on its own (the self-collision term of dgfs_collide)
+    pl->proj_ginv_self.resize(ns);
+    for (int p = 0; p < ns; ++p)
+      if (!projection_ginv(pl, std::vector<int>{p}, pl->proj_ginv_self[p])) {
+        set_error("conservation constraints are singular");
+        delete pl;
+        return DGFS_EINVAL;
+      }
   }
 
   // convert to the compute type and upload in one allocation

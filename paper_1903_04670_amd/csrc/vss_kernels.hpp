@@ -58,8 +58,12 @@ __device__ __forceinline__ void gain_yz_vss_body(const PipeArgs &a, int jx, int 
         C<T> h[H];
 #pragma unroll
         for (int n = 0; n < H; ++n) h[n] = src[(2 * n + p) * N + c];
+        if constexpr (sizeof(T) == 8 && N % 4 == 0 && N >= 8) {
+          col_phases_rec<T, N>(h, ph, zph, p);
+        } else {
 #pragma unroll
-        for (int n = 0; n < H; ++n) h[n] = cmul(h[n], cmul(ph[2 * n + p], zph));
+          for (int n = 0; n < H; ++n) h[n] = cmul(h[n], cmul(ph[2 * n + p], zph));
+        }
         fft_pair<N, +1>(h, p);
 #pragma unroll
         for (int k = 0; k < H; ++k) lds[g][p * H + k][c] = h[k];

@@ -40,6 +40,16 @@ class Mesh(ct.Structure):
                 ("u_right", ct.c_double * 3), ("T_right", ct.c_double)]
 
 
+class Mesh2D(ct.Structure):
+    _fields_ = [("Kx", ct.c_int32), ("Ky", ct.c_int32), ("x_left", ct.c_double), ("x_right", ct.c_double),
+                ("y_bottom", ct.c_double), ("y_top", ct.c_double), ("periodic_x", ct.c_int32),
+                ("periodic_y", ct.c_int32),
+                ("u_left", ct.c_double * 3), ("T_left", ct.c_double),
+                ("u_right", ct.c_double * 3), ("T_right", ct.c_double),
+                ("u_bottom", ct.c_double * 3), ("T_bottom", ct.c_double),
+                ("u_top", ct.c_double * 3), ("T_top", ct.c_double)]
+
+
 class Item(ct.Structure):
     _fields_ = [("plan", ct.c_int32), ("p", ct.c_int32), ("q", ct.c_int32), ("n_nodes", ct.c_int64),
                 ("fp", ct.c_void_p), ("fq", ct.c_void_p), ("node_stride", ct.c_int64),
@@ -62,6 +72,10 @@ lib.dgfs_rhs.argtypes = [_vp, ct.POINTER(Mesh), _i64, _vp, _vp, _u32, _vp, _sz, 
 lib.dgfs_rhs.restype = ct.c_int
 lib.dgfs_step.argtypes = [_vp, ct.POINTER(Mesh), _i64, _vp, ct.c_double, _i32, _u32, _vp, _sz, _vp]
 lib.dgfs_step.restype = ct.c_int
+lib.dgfs_rhs_2d.argtypes = [_vp, ct.POINTER(Mesh2D), _i64, _vp, _vp, _u32, _vp, _sz, _vp]
+lib.dgfs_rhs_2d.restype = ct.c_int
+lib.dgfs_step_2d.argtypes = [_vp, ct.POINTER(Mesh2D), _i64, _vp, ct.c_double, _i32, _u32, _vp, _sz, _vp]
+lib.dgfs_step_2d.restype = ct.c_int
 lib.dgfs_batched_workspace_bytes.argtypes = [ct.POINTER(_vp), _i32, ct.POINTER(Item), _i64]
 lib.dgfs_batched_workspace_bytes.restype = _sz
 lib.dgfs_collide_batched.argtypes = [ct.POINTER(_vp), _i32, ct.POINTER(Item), _i64, _u32, _vp, _sz, _vp]
@@ -83,7 +97,7 @@ lib.dgfs_plan_table.restype = ct.c_int
 EXPORTED = ["dgfs_plan_create", "dgfs_plan_destroy", "dgfs_workspace_bytes", "dgfs_collide",
             "dgfs_collide_vjp", "dgfs_rhs", "dgfs_step", "dgfs_batched_workspace_bytes",
             "dgfs_collide_batched", "dgfs_last_error", "dgfs_sphere_set", "dgfs_plan_table",
-            "dgfs_profile_enable", "dgfs_profile_read", "dgfs_autotune"]
+            "dgfs_profile_enable", "dgfs_profile_read", "dgfs_autotune", "dgfs_rhs_2d", "dgfs_step_2d"]
 
 
 def profile_enable(on=True):
@@ -215,10 +229,43 @@ def _torch():
     return torch
 
 
-def _stream_ptr(stream):
-    torch = _torch()
-    s = stream if stream is not None else torch.cuda.current_stream()
-    return ct.c_void_p(s.cuda_stream)
+class _Launch:
+    """Stream handling of one library call.
+
+    Without an explicit stream the call runs on torch's current stream.
+    With a stream `s` other than the current one: `s` first waits for the
+    work already queued on the current stream (which produced the inputs);
+    buffers the binding allocates (outputs, workspace) are allocated while
+    `s` is current, so the caching allocator ties them to `s`; and the
+    caller's tensors are recorded on `s`, so their memory is not handed out
+    again while `s` still uses it.  Use as a context manager around the
+    allocations and the call."""
+
+    def __init__(self, stream, *tensors):
+        torch = _torch()
+        cur = torch.cuda.current_stream()
+        self.side = stream is not None and stream != cur
+        self.stream = stream if self.side else cur
+        if self.side:
+            self.stream.wait_stream(cur)
+            for t in tensors:
+                if t is not None:
+                    t.record_stream(self.stream)
+        self._ctx = torch.cuda.stream(self.stream) if self.side else None
+
+    @property
+    def ptr(self):
+        return ct.c_void_p(self.stream.cuda_stream)
+
+    def __enter__(self):
+        if self._ctx is not None:
+            self._ctx.__enter__()
+        return self
+
+    def __exit__(self, *exc):
+        if self._ctx is not None:
+            return self._ctx.__exit__(*exc)
+        return False
 
 
 def workspace(plan, n_nodes, op=OP_COLLIDE, device="cuda"):
@@ -238,9 +285,12 @@ def _node_view(t, N):
     return ct.c_void_p(t.data_ptr()), (t.stride(0) if t.dim() == 4 else N ** 3)
 
 
-def collide(plan, p, q, fp, fq, out=None, accumulate=False, check=False, ws=None, stream=None):
+def collide(plan, p, q, fp, fq, out=None, accumulate=False, project=False, check=False, ws=None, stream=None):
     """Q^{pq}(f^p, f^q) for every node: fp, fq, out are [n_nodes, N, N, N]
-    float64 CUDA tensors (views with a node stride are fine)."""
+    float64 CUDA tensors (views with a node stride are fine).  project:
+    conservation projection of the result (the mass of species p; for the
+    self-collision of one array, p == q and fp is fq, also momentum and
+    energy)."""
     torch = _torch()
     if fp.dim() == 3:
         fp, fq = fp[None], fq[None]
@@ -253,14 +303,15 @@ def collide(plan, p, q, fp, fq, out=None, accumulate=False, check=False, ws=None
     pq_, sq = _node_view(fq, plan.N)
     if sf != sq and n_nodes > 1:
         raise ValueError("fp and fq must share the node stride")
-    if out is None:
-        out = torch.zeros((n_nodes, plan.N, plan.N, plan.N), dtype=torch.float64, device=fp.device)
-    po, so = _node_view(out, plan.N)
-    if ws is None:
-        ws = workspace(plan, n_nodes, OP_COLLIDE, fp.device)
-    flags = (ACCUMULATE if accumulate else 0) | (CHECK if check else 0)
-    _check(lib.dgfs_collide(plan.handle, n_nodes, p, q, pf, pq_, sf, po, so, flags,
-                            ct.c_void_p(ws.data_ptr()), ws.numel(), _stream_ptr(stream)), "dgfs_collide")
+    with _Launch(stream, fp, fq, out, ws) as run:
+        if out is None:
+            out = torch.zeros((n_nodes, plan.N, plan.N, plan.N), dtype=torch.float64, device=fp.device)
+        po, so = _node_view(out, plan.N)
+        if ws is None:
+            ws = workspace(plan, n_nodes, OP_COLLIDE, fp.device)
+        flags = (ACCUMULATE if accumulate else 0) | (PROJECT if project else 0) | (CHECK if check else 0)
+        _check(lib.dgfs_collide(plan.handle, n_nodes, p, q, pf, pq_, sf, po, so, flags,
+                                ct.c_void_p(ws.data_ptr()), ws.numel(), run.ptr), "dgfs_collide")
     return out
 
 
@@ -273,6 +324,53 @@ def make_mesh(K, x_left=0.0, x_right=1.0, u_left=(0.0, -0.5, 0.0), T_left=1.0,
     m.u_right[:] = [float(v) for v in u_right]
     m.T_left, m.T_right = float(T_left), float(T_right)
     return m
+
+
+def make_mesh2d(Kx, Ky, x=(0.0, 1.0), y=(0.0, 1.0), periodic=(False, True), walls=None):
+    """2-D mesh: Kx x Ky rectangles on x[0]..x[1] by y[0]..y[1]; periodic
+    (periodic_x, periodic_y); walls {"left"|"right"|"bottom"|"top": (u_w,
+    T_w)} for the non-periodic sides."""
+    m = Mesh2D()
+    m.Kx, m.Ky = int(Kx), int(Ky)
+    m.x_left, m.x_right = float(x[0]), float(x[1])
+    m.y_bottom, m.y_top = float(y[0]), float(y[1])
+    m.periodic_x, m.periodic_y = int(bool(periodic[0])), int(bool(periodic[1]))
+    walls = walls or {}
+    for side in ("left", "right", "bottom", "top"):
+        uw, Tw = walls.get(side, ((0.0, 0.0, 0.0), 1.0))
+        getattr(m, "u_" + side)[:] = [float(v) for v in uw]
+        setattr(m, "T_" + side, float(Tw))
+    return m
+
+
+def rhs_2d(plan, F, mesh, out=None, project=False, check=False, ws=None, stream=None):
+    """dF/dt on a 2-D mesh (transport in x and y + sum_q Q^{pq});
+    F [Kx Ky (P+1)^2, ns, N, N, N]."""
+    torch = _torch()
+    n = _state(plan, F)
+    with _Launch(stream, F, out, ws) as run:
+        if out is None:
+            out = torch.empty_like(F)
+        if ws is None:
+            ws = workspace(plan, n, OP_RHS, F.device)
+        flags = (PROJECT if project else 0) | (CHECK if check else 0)
+        _check(lib.dgfs_rhs_2d(plan.handle, ct.byref(mesh), n, ct.c_void_p(F.data_ptr()),
+                               ct.c_void_p(out.data_ptr()), flags, ct.c_void_p(ws.data_ptr()), ws.numel(),
+                               run.ptr), "dgfs_rhs_2d")
+    return out
+
+
+def step_2d(plan, F, dt, mesh, n_steps=1, project=False, euler=False, check=False, ws=None, stream=None):
+    """n_steps SSP-RK3 (or Euler) steps on F in place on a 2-D mesh."""
+    n = _state(plan, F)
+    with _Launch(stream, F, ws) as run:
+        if ws is None:
+            ws = workspace(plan, n, OP_STEP, F.device)
+        flags = (PROJECT if project else 0) | (EULER if euler else 0) | (CHECK if check else 0)
+        _check(lib.dgfs_step_2d(plan.handle, ct.byref(mesh), n, ct.c_void_p(F.data_ptr()), float(dt),
+                                int(n_steps), flags, ct.c_void_p(ws.data_ptr()), ws.numel(), run.ptr),
+               "dgfs_step_2d")
+    return F
 
 
 def _state(plan, F):
@@ -288,26 +386,28 @@ def rhs(plan, F, mesh=None, out=None, project=False, check=False, ws=None, strea
     """dF/dt = DG transport (if mesh) + sum_q Q^{pq}; F [n_nodes, ns, N, N, N]."""
     torch = _torch()
     n = _state(plan, F)
-    if out is None:
-        out = torch.empty_like(F)
-    if ws is None:
-        ws = workspace(plan, n, OP_RHS, F.device)
-    flags = (PROJECT if project else 0) | (CHECK if check else 0)
-    _check(lib.dgfs_rhs(plan.handle, ct.byref(mesh) if mesh is not None else None, n,
-                        ct.c_void_p(F.data_ptr()), ct.c_void_p(out.data_ptr()), flags,
-                        ct.c_void_p(ws.data_ptr()), ws.numel(), _stream_ptr(stream)), "dgfs_rhs")
+    with _Launch(stream, F, out, ws) as run:
+        if out is None:
+            out = torch.empty_like(F)
+        if ws is None:
+            ws = workspace(plan, n, OP_RHS, F.device)
+        flags = (PROJECT if project else 0) | (CHECK if check else 0)
+        _check(lib.dgfs_rhs(plan.handle, ct.byref(mesh) if mesh is not None else None, n,
+                            ct.c_void_p(F.data_ptr()), ct.c_void_p(out.data_ptr()), flags,
+                            ct.c_void_p(ws.data_ptr()), ws.numel(), run.ptr), "dgfs_rhs")
     return out
 
 
 def step(plan, F, dt, n_steps=1, mesh=None, project=False, euler=False, check=False, ws=None, stream=None):
     """n_steps SSP-RK3 (or Euler) steps on F in place."""
     n = _state(plan, F)
-    if ws is None:
-        ws = workspace(plan, n, OP_STEP, F.device)
-    flags = (PROJECT if project else 0) | (EULER if euler else 0) | (CHECK if check else 0)
-    _check(lib.dgfs_step(plan.handle, ct.byref(mesh) if mesh is not None else None, n,
-                         ct.c_void_p(F.data_ptr()), float(dt), int(n_steps), flags,
-                         ct.c_void_p(ws.data_ptr()), ws.numel(), _stream_ptr(stream)), "dgfs_step")
+    with _Launch(stream, F, ws) as run:
+        if ws is None:
+            ws = workspace(plan, n, OP_STEP, F.device)
+        flags = (PROJECT if project else 0) | (EULER if euler else 0) | (CHECK if check else 0)
+        _check(lib.dgfs_step(plan.handle, ct.byref(mesh) if mesh is not None else None, n,
+                             ct.c_void_p(F.data_ptr()), float(dt), int(n_steps), flags,
+                             ct.c_void_p(ws.data_ptr()), ws.numel(), run.ptr), "dgfs_step")
     return F
 
 
@@ -324,19 +424,20 @@ def collide_vjp(plan, p, q, fp, fq, wbar, grad_fp=None, grad_fq=None, accumulate
     if n > 1 and sf != sq:
         raise ValueError("fp and fq must share the node stride")
     shape = (n, plan.N, plan.N, plan.N)
-    if grad_fp is None:
-        grad_fp = torch.zeros(shape, dtype=torch.float64, device=fp.device)
-    if grad_fq is None:
-        grad_fq = torch.zeros(shape, dtype=torch.float64, device=fp.device)
-    pgf, sgf = _node_view(grad_fp, plan.N)
-    pgq, sgq = _node_view(grad_fq, plan.N)
-    if n > 1 and sgf != sgq:
-        raise ValueError("gradients must share the node stride")
-    if ws is None:
-        ws = workspace(plan, n, OP_VJP, fp.device)
-    _check(lib.dgfs_collide_vjp(plan.handle, n, p, q, pf, pq_, sf, pw, sw, pgf, pgq, sgf,
-                                ACCUMULATE if accumulate else 0, ct.c_void_p(ws.data_ptr()), ws.numel(),
-                                _stream_ptr(stream)), "dgfs_collide_vjp")
+    with _Launch(stream, fp, fq, wbar, grad_fp, grad_fq, ws) as run:
+        if grad_fp is None:
+            grad_fp = torch.zeros(shape, dtype=torch.float64, device=fp.device)
+        if grad_fq is None:
+            grad_fq = torch.zeros(shape, dtype=torch.float64, device=fp.device)
+        pgf, sgf = _node_view(grad_fp, plan.N)
+        pgq, sgq = _node_view(grad_fq, plan.N)
+        if n > 1 and sgf != sgq:
+            raise ValueError("gradients must share the node stride")
+        if ws is None:
+            ws = workspace(plan, n, OP_VJP, fp.device)
+        _check(lib.dgfs_collide_vjp(plan.handle, n, p, q, pf, pq_, sf, pw, sw, pgf, pgq, sgf,
+                                    ACCUMULATE if accumulate else 0, ct.c_void_p(ws.data_ptr()), ws.numel(),
+                                    run.ptr), "dgfs_collide_vjp")
     return grad_fp, grad_fq
 
 
@@ -392,29 +493,34 @@ def collide_batched(plans, items, accumulate=False, ws=None, stream=None):
             raise ValueError("item %d: fp and fq must share the node stride" % i)
         arr[i] = Item(k, p, q, fp.shape[0], pf, pq_, sf, po, so)
     n = len(items)
-    if ws is None:
-        nb = lib.dgfs_batched_workspace_bytes(handles, len(plans), arr, n)
-        if nb == 0 and n:
-            raise DGFSError(EINVAL, "dgfs_batched_workspace_bytes")
-        ws = torch.empty(max(nb, 256), dtype=torch.uint8, device="cuda")
-    _check(lib.dgfs_collide_batched(handles, len(plans), arr, n, ACCUMULATE if accumulate else 0,
-                                    ct.c_void_p(ws.data_ptr()), ws.numel(), _stream_ptr(stream)),
-           "dgfs_collide_batched")
+    tensors = [t for it in items for t in it[3:6]]
+    with _Launch(stream, ws, *tensors) as run:
+        if ws is None:
+            nb = lib.dgfs_batched_workspace_bytes(handles, len(plans), arr, n)
+            if nb == 0 and n:
+                raise DGFSError(EINVAL, "dgfs_batched_workspace_bytes")
+            ws = torch.empty(max(nb, 256), dtype=torch.uint8, device="cuda")
+        _check(lib.dgfs_collide_batched(handles, len(plans), arr, n, ACCUMULATE if accumulate else 0,
+                                        ct.c_void_p(ws.data_ptr()), ws.numel(), run.ptr),
+               "dgfs_collide_batched")
     return ws
 
 
 def autotune(plan, p, q, fp, fq, out, ws=None, stream=None):
-    """Pick the chunk width (evaluations per launch) for this plan by timing
-    dgfs_collide on the given [n_nodes, N, N, N] inputs; returns it."""
+    """Pick the launch schedule for this plan by timing dgfs_collide on the
+    given [n_nodes, N, N, N] inputs; returns (chunk width in evaluations
+    per launch, x-shift split or 0 for the default, gain_x fusion 0/1 or -1
+    for the default)."""
     torch = _torch()
     n = fp.shape[0]
     pf, sf = _node_view(fp, plan.N)
     pq_, _ = _node_view(fq, plan.N)
     po, so = _node_view(out, plan.N)
-    if ws is None:
-        # room for the widest candidate
-        ws = torch.empty(max(plan.workspace_bytes(n), 256) * 4, dtype=torch.uint8, device=fp.device)
-    chosen = ct.c_int32(0)
-    _check(lib.dgfs_autotune(plan.handle, n, p, q, pf, pq_, sf, po, so, ct.c_void_p(ws.data_ptr()), ws.numel(),
-                             _stream_ptr(stream), ct.byref(chosen)), "dgfs_autotune")
-    return int(chosen.value)
+    chosen = (ct.c_int32 * 3)()
+    with _Launch(stream, fp, fq, out, ws) as run:
+        if ws is None:
+            # room for the widest candidate
+            ws = torch.empty(max(plan.workspace_bytes(n), 256) * 4, dtype=torch.uint8, device=fp.device)
+        _check(lib.dgfs_autotune(plan.handle, n, p, q, pf, pq_, sf, po, so, ct.c_void_p(ws.data_ptr()),
+                                 ws.numel(), run.ptr, chosen), "dgfs_autotune")
+    return tuple(int(v) for v in chosen)

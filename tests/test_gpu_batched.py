@@ -65,18 +65,19 @@ def test_batched_small_mixed_sizes(torch_cuda, precision):
                 assert rel_linf(got[i], ref) <= 1e-11
 
 
-@pytest.mark.parametrize("n_inst", [96, 1024])
-def test_batched_uneven_instances_N16_24_32(torch_cuda, n_inst):
+@pytest.mark.parametrize("n_inst,precision", [(96, "fp64"), (1024, "fp64"), (1024, "fp32")])
+def test_batched_uneven_instances_N16_24_32(torch_cuda, n_inst, precision):
     """Space-homogeneous instances drawn like the batching workload (N in
     {16, 24, 32}, 1-3 species, N_rho in {8, 16}, icosahedron), 96 of them
     and the workload's full 1024 in the launch configuration the benchmark
     times: the batched launch equals per-instance launches bit for bit; in
     the 96-instance case 16 instances with N <= 24 (all their ordered
     pairs) and one pair of an N = 32 instance are checked against the
-    oracle."""
+    oracle.  The FP32-mixed plans run the same 1024 instances, also bit for
+    bit against their per-instance launches."""
     torch = torch_cuda
     insts = wl.batched_instances(n_inst=n_inst)
-    plans, items, outs_b, outs_s = _run(torch, insts, "fp64")
+    plans, items, outs_b, outs_s = _run(torch, insts, precision)
     assert len(items) > n_inst
     for ob, os_ in zip(outs_b, outs_s):
         assert torch.equal(ob, os_)

@@ -67,6 +67,94 @@ def test_radix5_radix7_grids(torch_cuda, N, kind):
         assert rel_linf(got[0], ref) <= TOL, (N, p, q)
 
 
+def test_N48_all_pairs(torch_cuda):
+    """N = 48 (the accuracy study's and the precision workload's grid),
+    icosahedron, N_rho = 2, all four ordered pairs of two species on one
+    node, against the oracle (the FP64 kernels instantiated for N = 48)."""
+    cfg = small_config(48, ns=2, M_kind="icosahedron", Nrho=2, seed=48, n_nodes=1)
+    opl = oracle_pairs(cfg)
+    pl = gpu_plan(cfg)
+    for p in range(2):
+        for q in range(2):
+            got = run_gpu(torch_cuda, pl, cfg["F"], p, q)
+            ref = oracle_collide(opl[p][q], cfg["F"][0, p], cfg["F"][0, q])
+            err = rel_linf(got[0], ref)
+            print("N=48 (%d,%d): rel Linf %.3e" % (p, q, err))
+            assert err <= TOL, (p, q, err)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_collide_project(torch_cuda, precision):
+    """DGFS_PROJECT on dgfs_collide through the C ABI: the self-collision of
+    one array is projected onto zero mass, momentum and energy change, a
+    cross or two-array term onto zero mass change, each against the
+    oracle's projection of the oracle's (FP64) or the library's own
+    unprojected (FP32-mixed) term; with DGFS_ACCUMULATE the projected term
+    is added."""
+    from oracle import conservation as cons
+    from paper_1903_04670_amd import dgfs
+    torch = torch_cuda
+    cfg = small_config(12, ns=2, M_kind="icosahedron", Nrho=4, seed=31, n_nodes=3)
+    N, L = cfg["N"], cfg["L"]
+    opl = oracle_pairs(cfg)
+    pl = gpu_plan(cfg, precision=precision)
+    F = torch.from_numpy(cfg["F"]).cuda()
+    tol = TOL if precision == "fp64" else 1e-13
+    for p, q, rows in [(0, 0, "all"), (1, 1, "all"), (0, 1, "mass"), (1, 0, "mass")]:
+        got = dgfs.collide(pl, p, q, F[:, p], F[:, q], project=True).cpu().numpy()
+        plain = dgfs.collide(pl, p, q, F[:, p], F[:, q]).cpu().numpy()
+        for i in range(3):
+            base = oracle_collide(opl[p][q], cfg["F"][i, p], cfg["F"][i, q]) if precision == "fp64" else plain[i]
+            ref = cons.project(base[None], N, L, [cfg["masses"][p]], rows=rows)[0]
+            err = rel_linf(got[i], ref)
+            assert err <= tol, (p, q, i, err)
+            mom = cons.moments(got[i][None], N, L, [cfg["masses"][p]])
+            scale = cons.moments(np.abs(got[i])[None], N, L, [cfg["masses"][p]])
+            k = 5 if rows == "all" else 1
+            assert np.max(np.abs(mom[:k])) <= 1e-12 * np.max(np.abs(scale)), (p, q, i)
+    # two different arrays for p == q conserve mass only
+    got = dgfs.collide(pl, 0, 0, F[:, 0], F[:, 1], project=True).cpu().numpy()
+    plain = dgfs.collide(pl, 0, 0, F[:, 0], F[:, 1]).cpu().numpy()
+    ref = cons.project(plain[:1], N, L, [cfg["masses"][0]], rows="mass")[0]
+    assert rel_linf(got[0], ref) <= 1e-13
+    # accumulate
+    base = torch.randn(3, N, N, N, dtype=torch.float64, device="cuda")
+    acc = base.clone()
+    proj = dgfs.collide(pl, 1, 0, F[:, 1], F[:, 0], project=True)
+    dgfs.collide(pl, 1, 0, F[:, 1], F[:, 0], out=acc, accumulate=True, project=True)
+    torch.cuda.synchronize()
+    assert torch.allclose(acc, base + proj, rtol=0, atol=1e-15)
+
+
+def test_side_stream_calls(torch_cuda):
+    """collide and step called with a non-default stream: the inputs are
+    written on the current stream just before, the binding allocates the
+    outputs and workspace for the side stream, and the results equal the
+    oracle's and the default-stream results."""
+    from oracle.collide import mixture_collision
+    from paper_1903_04670_amd import dgfs
+    torch = torch_cuda
+    cfg = small_config(8, ns=2, M_kind="icosahedron", Nrho=3, seed=33, n_nodes=4)
+    opl = oracle_pairs(cfg)
+    pl = gpu_plan(cfg)
+    side = torch.cuda.Stream()
+    for rep in range(3):
+        F = torch.empty((4, 2, 8, 8, 8), dtype=torch.float64, device="cuda")
+        F.copy_(torch.from_numpy(cfg["F"]))          # queued on the current stream
+        q = dgfs.collide(pl, 0, 1, F[:, 0], F[:, 1], stream=side)
+        side.synchronize()
+        got = q.cpu().numpy()
+        for i in range(4):
+            assert rel_linf(got[i], oracle_collide(opl[0][1], cfg["F"][i, 0], cfg["F"][i, 1])) <= TOL
+        del F
+    # a forward-Euler step on the side stream against the oracle's
+    F = torch.from_numpy(cfg["F"]).cuda()
+    ref = cfg["F"] + 1e-3 * mixture_collision(opl, cfg["F"])
+    dgfs.step(pl, F, 1e-3, 1, euler=True, stream=side)
+    side.synchronize()
+    assert rel_linf(F.cpu().numpy(), ref) <= TOL
+
+
 def test_couette_shape_N32_all_pairs(torch_cuda):
     """N = 32, icosahedron M = 12, N_rho = 16, two species: one node, all
     four ordered pairs, against the oracle."""
@@ -156,30 +244,44 @@ def test_fp32_mixed_radix5_radix7_grids(torch_cuda, N):
         assert err_q <= 5e-4
 
 
-def test_autotune_schedule(torch_cuda, tmp_path, monkeypatch):
-    """The autotuner picks one of its candidate chunk widths, stores it in the
-    cache, and the tuned plan gives bit-identical results."""
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_autotune_schedule(torch_cuda, tmp_path, monkeypatch, precision):
+    """The autotuner searches chunk width, x-shift split and the fused
+    k_gain_x pass, stores its pick in the cache, and every schedule (the
+    tuned one, each split, each fusion setting, a cached one) gives
+    bit-identical results, for a single cross pair and for the symmetric
+    two-species right-hand side (mirrored slots, half-set self pairs)."""
     from paper_1903_04670_amd import dgfs
     torch = torch_cuda
     monkeypatch.setenv("DGFS_TUNE_CACHE", str(tmp_path / "tune.txt"))
     cfg = small_config(12, ns=2, Nrho=4, seed=12, n_nodes=40)
-    pl = gpu_plan(cfg)
+    pl = gpu_plan(cfg, precision=precision)
     F = torch.from_numpy(cfg["F"]).cuda()
     ref = dgfs.collide(pl, 0, 1, F[:, 0], F[:, 1])
+    ref_rhs = dgfs.rhs(pl, F)
     out = torch.empty_like(ref)
-    chosen = dgfs.autotune(pl, 0, 1, F[:, 0], F[:, 1], out)
-    assert chosen in (8, 16, 32, 64, 128, 256)
-    assert (tmp_path / "tune.txt").read_text().strip().endswith("|%d" % chosen)
-    again = dgfs.collide(pl, 0, 1, F[:, 0], F[:, 1])
+    width, split, fuse = dgfs.autotune(pl, 0, 1, F[:, 0], F[:, 1], out)
+    assert width in (8, 16, 32, 64, 128, 256)
+    assert split in (0, 1, 2, 4, 8) and fuse in (-1, 0, 1)
+    assert (tmp_path / "tune.txt").read_text().strip().endswith("|%d,%d,%d" % (width, split, fuse))
     torch.cuda.synchronize()
-    assert torch.equal(again, ref)
-    pl2 = gpu_plan(cfg)  # picks the cached schedule up
+    assert torch.equal(dgfs.collide(pl, 0, 1, F[:, 0], F[:, 1]), ref)
+    assert torch.equal(dgfs.rhs(pl, F), ref_rhs)
+    pl2 = gpu_plan(cfg, precision=precision)  # picks the cached schedule up
     assert torch.equal(dgfs.collide(pl2, 0, 1, F[:, 0], F[:, 1]), ref)
-    # entries outside the candidate range are ignored when a plan loads the cache
+    # every split and fusion setting, written to the cache and read back
     key = (tmp_path / "tune.txt").read_text().strip().rsplit("|", 1)[0]
+    for s in (1, 2, 4, 8):
+        for f in (0, 1):
+            with open(tmp_path / "tune.txt", "a") as fh:
+                fh.write("%s|16,%d,%d\n" % (key, s, f))
+            plx = gpu_plan(cfg, precision=precision)
+            assert torch.equal(dgfs.collide(plx, 0, 1, F[:, 0], F[:, 1]), ref), (s, f)
+            assert torch.equal(dgfs.rhs(plx, F), ref_rhs), (s, f)
+    # entries outside the candidate ranges are ignored when a plan loads the cache
     with open(tmp_path / "tune.txt", "a") as fh:
-        fh.write("%s|0\n%s|-7\n%s|999999\n%s|x\n" % (key, key, key, key))
-    pl3 = gpu_plan(cfg)
+        fh.write("%s|0\n%s|-7,3,9\n%s|999999\n%s|x\n" % (key, key, key, key))
+    pl3 = gpu_plan(cfg, precision=precision)
     assert torch.equal(dgfs.collide(pl3, 0, 1, F[:, 0], F[:, 1]), ref)
 
 

@@ -1,0 +1,133 @@
+"""The 2-D (x, y) DG transport on the GPU (dgfs_rhs_2d / dgfs_step_2d):
+tensor Gauss-Lobatto nodes, upwind faces, diffuse walls or periodic sides,
+against the oracle's Box2D (which reduces to the pinned 1-D operator and
+converges at order P + 1), with the mixture collision term of the oracle;
+and the precision workload's full 2-D shape (16 x 8 elements, P = 1, 512
+nodes, three species, VSS, N = 48) for conservation of every species' mass
+in a closed box."""
+import numpy as np
+import pytest
+
+from helpers import gpu_plan, oracle_pairs, rel_linf, small_config
+from oracle import dg
+from oracle.collide import mixture_collision
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-11
+
+WALLS = {"left": ((0.0, -0.4, 0.0), 1.0), "right": ((0.0, 0.5, 0.1), 1.2),
+         "bottom": ((0.3, 0.0, 0.0), 0.9), "top": ((-0.2, 0.0, 0.0), 1.1)}
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _case(Kx, Ky, P, periodic, N=8, ns=2, seed=0, extent=((0.0, 1.5), (-0.5, 0.5))):
+    n = Kx * Ky * (P + 1) ** 2
+    cfg = small_config(N, ns=ns, Nrho=3, seed=seed, n_nodes=n)
+    walls = {k: v for k, v in WALLS.items()
+             if not periodic[0 if k in ("left", "right") else 1]}
+    box = dg.Box2D(N, cfg["L"], cfg["masses"], Kx, Ky, P, extent=extent, periodic=periodic, walls=walls)
+    return cfg, box, walls
+
+
+@pytest.mark.parametrize("Kx,Ky,P,periodic", [(3, 2, 1, (False, True)), (2, 3, 2, (False, False)),
+                                              (4, 3, 1, (True, True)), (3, 2, 3, (True, False)),
+                                              (70, 1, 1, (False, True))])
+def test_rhs_2d_against_oracle(torch_cuda, Kx, Ky, P, periodic):
+    """Transport + mixture collision term against the oracle (70 x 1:
+    more elements than the kernel's 64 element slices)."""
+    from paper_1903_04670_amd import dgfs
+    torch = torch_cuda
+    cfg, box, walls = _case(Kx, Ky, P, periodic, seed=Kx * 10 + Ky)
+    opl = oracle_pairs(cfg)
+    pl = gpu_plan(cfg, dg_order=P)
+    mesh = dgfs.make_mesh2d(Kx, Ky, x=(0.0, 1.5), y=(-0.5, 0.5), periodic=periodic, walls=walls)
+    F = torch.from_numpy(cfg["F"]).cuda()
+    got = dgfs.rhs_2d(pl, F, mesh).cpu().numpy()
+    if Kx * Ky > 20:   # transport only for the long mesh (its collision term is the same kernel)
+        ref = box.transport_rhs(cfg["F"]) + mixture_collision(opl, cfg["F"])
+    else:
+        ref = box.rhs(cfg["F"], lambda G: mixture_collision(opl, G))
+    assert rel_linf(got, ref) <= TOL
+
+
+def test_step_2d_ssp_rk3_against_oracle(torch_cuda):
+    """Two SSP-RK3 steps (graph-replayed) in a closed box with four diffuse
+    walls, and one with the projection, against the oracle's steps."""
+    from oracle import conservation as cons
+    from paper_1903_04670_amd import dgfs
+    torch = torch_cuda
+    Kx, Ky, P = 2, 2, 1
+    cfg, box, walls = _case(Kx, Ky, P, (False, False), seed=5)
+    opl = oracle_pairs(cfg)
+    pl = gpu_plan(cfg, dg_order=P)
+    mesh = dgfs.make_mesh2d(Kx, Ky, x=(0.0, 1.5), y=(-0.5, 0.5), periodic=(False, False), walls=walls)
+    dt = 2e-3
+    coll = lambda G: mixture_collision(opl, G)
+    ref = cfg["F"]
+    for _ in range(2):
+        ref = dg.ssp_rk3(ref, dt, lambda G: box.rhs(G, coll))
+    F = torch.from_numpy(cfg["F"]).cuda()
+    dgfs.step_2d(pl, F, dt, mesh, n_steps=2)
+    assert rel_linf(F.cpu().numpy(), ref) <= TOL
+
+    def proj_coll(G):
+        Q = coll(G)
+        return np.stack([cons.project(Q[i], cfg["N"], cfg["L"], cfg["masses"]) for i in range(G.shape[0])])
+    ref = dg.ssp_rk3(cfg["F"], dt, lambda G: box.rhs(G, proj_coll))
+    F = torch.from_numpy(cfg["F"]).cuda()
+    dgfs.step_2d(pl, F, dt, mesh, n_steps=1, project=True)
+    assert rel_linf(F.cpu().numpy(), ref) <= TOL
+
+
+def test_mesh2d_validation(torch_cuda):
+    from paper_1903_04670_amd import dgfs
+    torch = torch_cuda
+    cfg, _, walls = _case(2, 2, 1, (False, True))
+    pl = gpu_plan(cfg, dg_order=1)
+    F = torch.from_numpy(cfg["F"]).cuda()
+    with pytest.raises(dgfs.DGFSError):   # node count does not match the mesh
+        dgfs.rhs_2d(pl, F, dgfs.make_mesh2d(3, 2, walls=walls))
+    with pytest.raises(dgfs.DGFSError):   # a wall with zero temperature
+        dgfs.rhs_2d(pl, F, dgfs.make_mesh2d(2, 2, periodic=(False, True), walls={"left": ((0, 0, 0), 0.0),
+                                                                                  "right": ((0, 0, 0), 1.0)}))
+    pl0 = gpu_plan(cfg, dg_order=0)
+    with pytest.raises(dgfs.DGFSError):   # the plan has no DG order
+        dgfs.rhs_2d(pl0, F, dgfs.make_mesh2d(2, 2, walls=walls))
+
+
+def test_precision_workload_2d_box_conserves_mass(torch_cuda):
+    """The precision workload's 2-D shape: 16 x 8 elements with P = 1 (512
+    nodes) on the unit square with four diffuse walls, three species
+    (masses 1, 2, 4), VSS alpha = 1.4, N = 48, Fibonacci M = 32,
+    N_rho = 24, FP32-mixed collision with the FP64 projection.  One forward
+    Euler step: finite, and the DG mass of every species (GLL weights) is
+    unchanged to round-off (the walls carry zero net mass flux and the
+    projected collision term conserves each species' mass)."""
+    from paper_1903_04670_amd import dgfs, workloads as wl
+    torch = torch_cuda
+    cfg = wl.precision_vss(n_nodes=512)
+    walls = {"left": ((0.0, -0.3, 0.0), 1.0), "right": ((0.0, 0.3, 0.0), 1.0),
+             "bottom": ((0.2, 0.0, 0.0), 1.0), "top": ((-0.2, 0.0, 0.0), 1.0)}
+    mesh = dgfs.make_mesh2d(16, 8, periodic=(False, False), walls=walls)
+    F = torch.from_numpy(cfg["F"]).cuda()
+    del cfg["F"]
+    pl = gpu_plan(cfg, dg_order=1, precision="fp32")
+    hx, hy = 1.0 / 16, 1.0 / 8
+
+    def masses(G):
+        # P = 1 GLL weights are 1, so every node carries hx hy / 4
+        return (G.sum(dim=(2, 3, 4)).sum(dim=0) * hx * hy / 4).cpu().numpy()
+    m0 = masses(F)
+    dgfs.step_2d(pl, F, 1e-3, mesh, n_steps=1, project=True, euler=True)
+    torch.cuda.synchronize()
+    assert bool(torch.isfinite(F).all())
+    m1 = masses(F)
+    print("species masses before %s after %s" % (m0, m1))
+    assert np.max(np.abs(m1 - m0) / m0) < 1e-12, (m0, m1)

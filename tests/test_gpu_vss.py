@@ -78,6 +78,59 @@ def test_vss_radix5_grid_N40(torch_cuda):
         assert rel_linf(got[0], ref) <= TOL, (p, q)
 
 
+def _vss_cfg5_shape(n_nodes=1, Nrho=2):
+    """The precision workload's collision shape (three species, masses 1, 2,
+    4, alpha = 1.4, N = 48, Fibonacci M = 32) with N_rho = 2: the kernels'
+    code paths depend on N and M, not on N_rho, and the oracle's VSS tables
+    then take about 15 s per pair."""
+    from paper_1903_04670_amd import workloads as wl
+    return wl.precision_vss(n_nodes=n_nodes, Nrho=Nrho)
+
+
+def _oracle_pair(cfg, p, q):
+    from oracle.collide import PairPlan
+    from oracle.quadrature import sphere_set
+    s, w = sphere_set(cfg["sphere"], cfg["M"])
+    return PairPlan(cfg["N"], cfg["L"], cfg["masses"][p], cfg["masses"][q], cfg["omega"][p][q],
+                    cfg["alpha"][p][q], cfg["Nrho"], s, w, R=cfg["R"][p][q])
+
+
+def test_vss_cfg5_shape_N48_against_oracle(torch_cuda):
+    """N = 48, Fibonacci M = 32, alpha = 1.4, three species: a cross pair
+    (masses 1 and 4) and a self pair, one node, FP64 against the oracle at
+    1e-11 (k_gain_yz_vss and k_gain_x_vss at N = 48)."""
+    from paper_1903_04670_amd import dgfs
+    torch = torch_cuda
+    cfg = _vss_cfg5_shape()
+    pl = gpu_plan(cfg)
+    F = torch.from_numpy(cfg["F"]).cuda()
+    for p, q in [(0, 2), (1, 1)]:
+        got = dgfs.collide(pl, p, q, F[:, p], F[:, q]).cpu().numpy()
+        ref = oracle_collide(_oracle_pair(cfg, p, q), cfg["F"][0, p], cfg["F"][0, q])
+        err = rel_linf(got[0], ref)
+        print("VSS N=48 M=32 (%d,%d): rel Linf %.3e" % (p, q, err))
+        assert err <= TOL, (p, q, err)
+
+
+def test_vss_cfg5_shape_N48_fp32_mixed_against_oracle(torch_cuda):
+    """The same shape in FP32-mixed against the FP64 oracle, within the
+    FP32 bounds stated for the VHS path: 2e-6 of the loss term, 5e-4 of Q."""
+    from oracle.collide import collide_gain_loss
+    from paper_1903_04670_amd import dgfs
+    torch = torch_cuda
+    cfg = _vss_cfg5_shape()
+    pl = gpu_plan(cfg, precision="fp32")
+    F = torch.from_numpy(cfg["F"]).cuda()
+    for p, q in [(0, 2), (1, 1)]:
+        got = dgfs.collide(pl, p, q, F[:, p], F[:, q]).cpu().numpy()[0]
+        gain, loss = collide_gain_loss(_oracle_pair(cfg, p, q), cfg["F"][0, p], cfg["F"][0, q])
+        ref = gain - loss
+        err_q = rel_linf(got, ref)
+        err_l = float(np.max(np.abs(got - ref)) / np.max(np.abs(loss)))
+        print("VSS N=48 fp32-mixed (%d,%d): rel to |Q| %.3e, rel to |loss| %.3e" % (p, q, err_q, err_l))
+        assert err_l <= 2e-6 and err_q <= 5e-4
+
+
 def test_vss_three_species_rhs_N16(torch_cuda):
     """Three species (masses 1, 2, 4), alpha = 1.4, Fibonacci M = 32,
     N_rho = 8 at N = 16: the mixture collision term against the oracle."""

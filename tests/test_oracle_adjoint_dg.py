@@ -175,3 +175,72 @@ def test_gain_part_is_symmetric_for_antipodal_sets(sphere, symmetric):
         assert abs(df - dg) <= 1e-10 * abs(df)
     else:
         assert abs(df - dg) > 1e-3 * abs(df)
+
+
+# ------------------------------------------------------------ 2-D box transport
+def test_box2d_reduces_to_the_1d_operator():
+    """Periodic in y with data independent of y: the 2-D transport equals the
+    pinned 1-D-x operator with the same walls at every y-node."""
+    N, L, masses, K, P = 6, 4.0, [1.0, 2.0], 5, 2
+    walls = {"left": ((0, -0.5, 0), 1.0), "right": ((0, 0.5, 0), 1.3)}
+    box = dg.Box2D(N, L, masses, K, 3, P, periodic=(False, True), walls=walls)
+    line = dg.Couette1D(N, L, masses, K, P, (0, -0.5, 0), (0, 0.5, 0), 1.0, 1.3)
+    rng = np.random.default_rng(7)
+    F1 = rng.random((K * (P + 1), 2, N, N, N)) + 0.5
+    # replicate along y: node ((ey Kx + ex)(P+1) + j)(P+1) + i <- 1-D node ex(P+1) + i
+    U1 = F1.reshape(K, P + 1, 2, N, N, N)
+    F2 = np.broadcast_to(U1[None, :, None], (3, K, P + 1, P + 1, 2, N, N, N)).reshape(-1, 2, N, N, N).copy()
+    d1 = line.transport_rhs(F1).reshape(K, P + 1, 2, N, N, N)
+    d2 = box.transport_rhs(F2).reshape(3, K, P + 1, P + 1, 2, N, N, N)
+    ref = np.broadcast_to(d1[None, :, None], d2.shape)
+    assert np.max(np.abs(d2 - ref)) <= 1e-13 * np.max(np.abs(d1))
+
+
+def _box_advect_error(K, P, T=0.25):
+    """f_t + c_x f_x + c_y f_y = 0 on the periodic unit square for the eight
+    velocities of an N = 2 grid (c = +-0.5 per axis): the exact solution is
+    the initial data translated by c t."""
+    N, L = 2, 1.0
+    box = dg.Box2D(N, L, [1.0], K, K, P, periodic=(True, True))
+    xy = box.node_xy()
+    cx, cy = box.cx, box.cy
+
+    def exact(t):
+        x = xy[:, 0][:, None, None, None] - cx[None] * t
+        y = xy[:, 1][:, None, None, None] - cy[None] * t
+        return (np.sin(2 * math.pi * x) * np.cos(2 * math.pi * y) + 2.0)[:, None]
+    F = exact(0.0)
+    h = 1.0 / K
+    dt = 0.05 * h / 0.5 / (P + 1) ** 2
+    n = int(math.ceil(T / dt))
+    for _ in range(n):
+        F = dg.ssp_rk3(F, T / n, box.transport_rhs)
+    return np.max(np.abs(F - exact(T)))
+
+
+def test_box2d_advection_converges():
+    P = 2
+    e = [_box_advect_error(K, P) for K in (4, 8, 16)]
+    rates = [math.log2(a / b) for a, b in zip(e, e[1:])]
+    assert min(rates) > P + 0.5, (e, rates)
+
+
+def test_box2d_closed_box_conserves_mass():
+    """Four diffuse walls (each node's inflow carries its outflow): the DG
+    mass of every species, sum over nodes of w_i w_j hx hy / 4 times the
+    velocity sum, does not change under the transport."""
+    N, L, K, P = 6, 4.0, 3, 1
+    walls = {"left": ((0, -0.3, 0), 1.0), "right": ((0, 0.4, 0), 1.2),
+             "bottom": ((0.2, 0, 0), 0.9), "top": ((-0.1, 0, 0.1), 1.1)}
+    box = dg.Box2D(N, L, [1.0, 3.0], K, 2, P, extent=((0.0, 1.5), (0.0, 1.0)),
+                   periodic=(False, False), walls=walls)
+    rng = np.random.default_rng(9)
+    F = rng.random((box.n_nodes(), 2, N, N, N)) + 0.1
+    d = box.transport_rhs(F)
+    w = np.array([1.0, 1.0])               # GLL weights for P = 1 (the trapezoid rule)
+    wn = np.outer(w, w).ravel()            # weights of (j, i)
+    wt = np.tile(wn, 3 * 2) * box.hx * box.hy / 4.0
+    for p in range(2):
+        rate = np.sum(wt[:, None] * d[:, p].reshape(box.n_nodes(), -1))
+        scale = np.sum(wt[:, None] * np.abs(d[:, p]).reshape(box.n_nodes(), -1))
+        assert abs(rate) < 1e-13 * scale, (p, rate, scale)
