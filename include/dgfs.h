@@ -171,6 +171,26 @@ dgfs_status dgfs_collide(dgfs_plan plan, int64_t n_nodes, int32_t p, int32_t q,
                          void *ws, size_t ws_bytes, void *stream);
 
 /*
+ * dgfs_collide for callers that cannot allocate device memory (code under
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): no
+ * workspace argument; the pipeline's arrays live in a 256 MiB device array
+ * of the library, one per GPU, held from the first call on that GPU until
+ * the process ends.  Same operator, arguments and results as dgfs_collide
+ * (bit for bit); nodes run in chunks that fit the array (N = 32, M = 12,
+ * N_rho = 16: 2 nodes per launch in FP64, 5 in FP32-mixed).  Calls no
+ * hipMalloc, hipFree or other allocating routine.
+ *   flags    DGFS_ACCUMULATE, DGFS_PROJECT (DGFS_CHECK, which allocates and
+ *            synchronises, is refused with DGFS_EINVAL)
+ * Returns DGFS_EUNSUPPORTED when one node needs more than 256 MiB (e.g.
+ * N = 48 with N_rho = 24 in FP64).  Every call on a GPU shares that GPU's
+ * array, which keeps the last call's contents: calls that overlap on one
+ * GPU (different streams or threads) race, so serialise them.
+ */
+dgfs_status dgfs_collide_noalloc(dgfs_plan plan, int64_t n_nodes, int32_t p, int32_t q, const double *fp,
+                                 const double *fq, int64_t node_stride, double *Q, int64_t out_stride,
+                                 uint32_t flags, void *stream);
+
+/*
  * Vector-Jacobian product of dgfs_collide: for a cotangent wbar (same layout
  * as Q) returns grad_fp = (dQ/df^p)^T wbar and grad_fq = (dQ/df^q)^T wbar.
  * Intermediates of the (r, m) loop are recomputed, not stored (VSS plans

@@ -65,6 +65,8 @@ lib.dgfs_workspace_bytes.argtypes = [_vp, _i64, _i32]
 lib.dgfs_workspace_bytes.restype = _sz
 lib.dgfs_collide.argtypes = [_vp, _i64, _i32, _i32, _vp, _vp, _i64, _vp, _i64, _u32, _vp, _sz, _vp]
 lib.dgfs_collide.restype = ct.c_int
+lib.dgfs_collide_noalloc.argtypes = [_vp, _i64, _i32, _i32, _vp, _vp, _i64, _vp, _i64, _u32, _vp]
+lib.dgfs_collide_noalloc.restype = ct.c_int
 lib.dgfs_collide_vjp.argtypes = [_vp, _i64, _i32, _i32, _vp, _vp, _i64, _vp, _i64, _vp, _vp, _i64, _u32,
                                  _vp, _sz, _vp]
 lib.dgfs_collide_vjp.restype = ct.c_int
@@ -97,7 +99,8 @@ lib.dgfs_plan_table.restype = ct.c_int
 EXPORTED = ["dgfs_plan_create", "dgfs_plan_destroy", "dgfs_workspace_bytes", "dgfs_collide",
             "dgfs_collide_vjp", "dgfs_rhs", "dgfs_step", "dgfs_batched_workspace_bytes",
             "dgfs_collide_batched", "dgfs_last_error", "dgfs_sphere_set", "dgfs_plan_table",
-            "dgfs_profile_enable", "dgfs_profile_read", "dgfs_autotune", "dgfs_rhs_2d", "dgfs_step_2d"]
+            "dgfs_profile_enable", "dgfs_profile_read", "dgfs_autotune", "dgfs_rhs_2d", "dgfs_step_2d",
+            "dgfs_collide_noalloc"]
 
 
 def profile_enable(on=True):
@@ -312,6 +315,24 @@ def collide(plan, p, q, fp, fq, out=None, accumulate=False, project=False, check
         flags = (ACCUMULATE if accumulate else 0) | (PROJECT if project else 0) | (CHECK if check else 0)
         _check(lib.dgfs_collide(plan.handle, n_nodes, p, q, pf, pq_, sf, po, so, flags,
                                 ct.c_void_p(ws.data_ptr()), ws.numel(), run.ptr), "dgfs_collide")
+    return out
+
+
+def collide_noalloc(plan, p, q, fp, fq, out, accumulate=False, project=False, stream=None):
+    """dgfs_collide_noalloc: Q^{pq} into `out` with the library's own device
+    scratch instead of a workspace (nothing is allocated by the library;
+    the caller passes the output).  Calls on one GPU must not overlap."""
+    if fp.dim() == 3:
+        fp, fq, out = fp[None], fq[None], out[None]
+    pf, sf = _node_view(fp, plan.N)
+    pq_, sq = _node_view(fq, plan.N)
+    po, so = _node_view(out, plan.N)
+    if sf != sq and fp.shape[0] > 1:
+        raise ValueError("fp and fq must share the node stride")
+    flags = (ACCUMULATE if accumulate else 0) | (PROJECT if project else 0)
+    with _Launch(stream, fp, fq, out) as run:
+        _check(lib.dgfs_collide_noalloc(plan.handle, fp.shape[0], p, q, pf, pq_, sf, po, so, flags, run.ptr),
+               "dgfs_collide_noalloc")
     return out
 
 
