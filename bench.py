@@ -46,6 +46,9 @@ def parse():
                          "vss: three-species VSS N = 48, M = 32, N_rho = 24; "
                          "table1: latency and 64-node throughput at the accuracy study's shapes; "
                          "box2d: one step of the 2-D box with the three-species VSS N = 48 collision term")
+    ap.add_argument("--autotune", action="store_true",
+                    help="run dgfs_autotune on each plan (cross pair, all nodes) before timing; the chosen "
+                         "schedule is reported")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device copy (reference for HBM byte counters)")
     return ap.parse_args()
@@ -207,6 +210,9 @@ def run(args):
                          precision=prec, nyquist_zero=nyq)
         project = prec == "fp32"
         F = F0.clone()
+        sched = None
+        if args.autotune:
+            sched = dgfs.autotune(plan, 0, 1, F[:, 0], F[:, 1], torch.empty_like(F[:, 0]))
         ws = dgfs.workspace(plan, n_nodes, dgfs.OP_STEP, dev)
         stream = torch.cuda.current_stream()
         for _ in range(args.warmup):
@@ -237,7 +243,7 @@ def run(args):
         torch.cuda.synchronize()
         ms_graph = (time.perf_counter() - t0) * 1e3 / args.steps
         out[prec + ("_nyq" if nyq else "")] = dict(ms=ms, ms_graph=ms_graph, kern=kern, finite=finite,
-                                                   plan=plan, sigma_x=plan.sigma[:, 0].copy())
+                                                   plan=plan, sigma_x=plan.sigma[:, 0].copy(), sched=sched)
     return cfg, evals_per_step, out
 
 
@@ -581,6 +587,8 @@ def main():
             "kernels_ms_per_step": {k: round(v[1] / args.steps, 4) for k, v in sorted(n64["kern"].items())},
             "kernels_ms_per_step_fp32": {k: round(v[1] / args.steps, 4) for k, v in sorted(n32["kern"].items())}},
         "finite": all(r["finite"] for r in res.values()),
+        "schedule": ("default" if not args.autotune else
+                     {k: dict(zip(("chunk_evals", "shift_split", "gain_x_fuse"), v["sched"])) for k, v in res.items()}),
     }
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(args.cpu_seconds)

@@ -184,6 +184,17 @@ __device__ __forceinline__ void col_phases_rec(cplx<T> (&h)[N / 2], const cplx<T
   }
 }
 
+// Streaming store of one complex value: the x-shifted arrays and the C_r
+// arrays are written once and read back by the next kernel from HBM (a
+// launch writes several GB), so the write need not allocate cache lines.
+template <typename T> __device__ __forceinline__ void store_stream(cplx<T> *dst, cplx<T> v) {
+  typedef T V2 __attribute__((ext_vector_type(2)));
+  V2 w;
+  w.x = v.x;
+  w.y = v.y;
+  __builtin_nontemporal_store(w, reinterpret_cast<V2 *>(dst));
+}
+
 // Compensated accumulation (used by the FP32 path): Kahan's summation with
 // the correction kept so that s + c is the running sum.  The rounding error
 // of each addition, y - (t - s), is recovered exactly and fed into the next
@@ -299,7 +310,7 @@ __device__ __forceinline__ void shift_x_body(const PipeArgs &a, int bx, int side
     C<T> *dst = X + (size_t)rs * n3;
     if (valid) {
 #pragma unroll
-      for (int k = 0; k < H; ++k) dst[(size_t)(2 * k + p) * N * N + pc] = w[k];
+      for (int k = 0; k < H; ++k) store_stream(&dst[(size_t)(2 * k + p) * N * N + pc], w[k]);
     }
   }
 }
@@ -645,7 +656,7 @@ __device__ __forceinline__ void gain_yz_body(const PipeArgs &a, int jx, int r, i
     fft_pair<N, -1>(h, p);
     C<T> *dst = static_cast<C<T> *>(a.Cb) + ((size_t)e * a.Nr + r) * n3 + (size_t)jx * N * N;
 #pragma unroll
-    for (int k = 0; k < H; ++k) dst[(p * H + k) * N + c] = h[k];
+    for (int k = 0; k < H; ++k) store_stream(&dst[(p * H + k) * N + c], h[k]);
   }
 }
 template <typename T, int N, int G, int NB = gain_bufs<T>(), bool PACK = false>

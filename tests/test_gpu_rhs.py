@@ -147,7 +147,7 @@ def test_projected_rhs_conserves(torch_cuda):
     ref = np.stack([cons.project(C[i], cfg["N"], cfg["L"], cfg["masses"]) for i in range(3)])
     pl = gpu_plan(cfg)
     got = dgfs.rhs(pl, torch.from_numpy(cfg["F"]).cuda(), project=True).cpu().numpy()
-    assert rel_linf(got, ref) <= 1e-10
+    assert rel_linf(got, ref) <= TOL
     for i in range(3):
         mom = cons.moments(got[i], cfg["N"], cfg["L"], cfg["masses"])
         scale = cons.moments(np.abs(C[i]), cfg["N"], cfg["L"], cfg["masses"])
