@@ -204,7 +204,13 @@ def run(args):
     n_nodes = F0.shape[0]
     evals_per_step = 3 * n_nodes * cfg["ns"] ** 2
     out = {}
-    for prec, nyq in (("fp64", False), ("fp32", False), ("fp64", True), ("fp32", True)):
+    for prec, nyq, nosym in (("fp64", False, False), ("fp32", False, False), ("fp64", True, False),
+                             ("fp32", True, False), ("fp64", False, True)):
+        # the last variant turns the reuse of gain sums off (every ordered pair
+        # sums over all M directions): the rate of a workload without the
+        # symmetry of this one
+        if nosym:
+            os.environ["DGFS_NO_SYMMETRY"] = "1"
         plan = dgfs.Plan(cfg["masses"], cfg["omega"], cfg["alpha"], cfg["N"], cfg["L"], cfg["Nrho"],
                          sphere=cfg["sphere"], M=cfg["M"], S=cfg["S"], R=cfg["R"], dg_order=cfg["P"],
                          precision=prec, nyquist_zero=nyq)
@@ -242,8 +248,11 @@ def run(args):
         dgfs.step(plan, F, cfg["dt"], args.steps, mesh=mesh, project=project, ws=ws)
         torch.cuda.synchronize()
         ms_graph = (time.perf_counter() - t0) * 1e3 / args.steps
-        out[prec + ("_nyq" if nyq else "")] = dict(ms=ms, ms_graph=ms_graph, kern=kern, finite=finite,
-                                                   plan=plan, sigma_x=plan.sigma[:, 0].copy(), sched=sched)
+        out[prec + ("_nyq" if nyq else "") + ("_nosym" if nosym else "")] = dict(
+            ms=ms, ms_graph=ms_graph, kern=kern, finite=finite, plan=plan, sigma_x=plan.sigma[:, 0].copy(),
+            sched=sched)
+        if nosym:
+            del os.environ["DGFS_NO_SYMMETRY"]
     return cfg, evals_per_step, out
 
 
@@ -369,8 +378,9 @@ def bench_vjp(args):
 def bench_batched(args):
     """1024 space-homogeneous instances of uneven size (N in {16, 24, 32},
     1-3 species, N_rho in {8, 16}, icosahedron): every ordered pair of every
-    instance, once through dgfs_collide_batched (one launch per stage per
-    workspace chunk) and once as one dgfs_collide call per item."""
+    instance through dgfs_collide_batched (one launch per stage per
+    workspace chunk), with the descriptor array prepared once (dgfs.Batch)
+    and built again per call, and once as one dgfs_collide call per item."""
     import torch
     from paper_1903_04670_amd import dgfs, workloads as wl
     insts = wl.batched_instances(n_inst=1024)
@@ -382,21 +392,34 @@ def bench_batched(args):
         for p in range(c["ns"]):
             for q in range(c["ns"]):
                 items.append((k, p, q, F[:, p], F[:, q], torch.empty(F[:, p].shape, dtype=torch.float64, device="cuda")))
-    ws = dgfs.collide_batched(plans, items)
+    batch = dgfs.Batch(plans, items)
+    ws = batch.run()
     ws1 = torch.empty(max(pl.workspace_bytes(1) for pl in plans), dtype=torch.uint8, device="cuda")
 
     def batched():
+        batch.run(ws=ws)
+
+    def batched_rebuilt():
+        # descriptor array built again on every call (dgfs.collide_batched)
         dgfs.collide_batched(plans, items, ws=ws)
 
     def single():
         for (k, p, q, fp, fq, out) in items:
             dgfs.collide(plans[k], p, q, fp, fq, out, ws=ws1)
     tb = _time_cuda(batched, args.steps, args.warmup)
+    tr = _time_cuda(batched_rebuilt, args.steps, 1)
     ts = _time_cuda(single, max(1, args.steps // 2), 1)
+    dgfs.profile_enable(True)
+    batch.run(ws=ws)
+    torch.cuda.synchronize()
+    kern = {k: round(v[1], 3) for k, v in sorted(dgfs.profile_read().items())}
+    dgfs.profile_enable(False)
     return {"metric": "collision evals/s, 1024 uneven space-homogeneous instances (FP64)",
             "value": round(len(items) / tb, 1), "unit": "collision evals/s",
+            "descriptors_rebuilt_per_call_evals_per_s": round(len(items) / tr, 1),
             "per_instance_launches_evals_per_s": round(len(items) / ts, 1), "evals": len(items),
-            "batched_ms": round(tb * 1e3, 3), "per_instance_ms": round(ts * 1e3, 3), "n_gpus": 1,
+            "batched_ms": round(tb * 1e3, 3), "per_instance_ms": round(ts * 1e3, 3),
+            "kernels_ms_per_call": kern, "n_gpus": 1,
             "dtype": "f64", "data": "synthetic", "config": {"workload": "1024 instances N in {16,24,32}"}}
 
 
@@ -522,7 +545,7 @@ def main():
               "MI355X; sharding across GPUs is described in the design notes, not implemented.", file=sys.stderr)
         sys.exit(2)
     cfg, evals_per_step, res = run(args)
-    r64, r32 = res["fp64"], res["fp32"]
+    r64, r32, rns = res["fp64"], res["fp32"], res["fp64_nosym"]
     n64, n32 = res["fp64_nyq"], res["fp32_nyq"]
     value = evals_per_step / (r64["ms"] / 1e3)
     gpp, gpq, gterms = gain_schedule(cfg)
@@ -574,6 +597,13 @@ def main():
             "fp64_TBps": round(value * model_bytes_per_eval(cfg["N"], cfg["M"], cfg["Nrho"], 8) / 1e12, 3),
             "fp32_mixed_TBps": round(value32 * model_bytes_per_eval(cfg["N"], cfg["M"], cfg["Nrho"], 4) / 1e12,
                                      3)},
+        "no_symmetry": {
+            "what": "FP64 step with the reuse of gain sums turned off: every ordered pair sums over all "
+                    "M = 12 directions (48 direction terms per node instead of 24); the rate of a workload "
+                    "without this one's antipodal sphere set and equal R_pq = R_qp",
+            "fp64_evals_per_s": round(evals_per_step / (rns["ms"] / 1e3), 1),
+            "graph_replay_fp64_evals_per_s": round(evals_per_step / (rns["ms_graph"] / 1e3), 1),
+            "direction_terms_per_node": cfg["ns"] * cfg["ns"] * cfg["M"]},
         "nyquist_zero": {
             "what": "variant operator, not the headline: the gain's translates drop the Nyquist planes of "
                     "fft(f), so u1, u2 are real and one complex transform gives both (real-packed k_gain_yz)",

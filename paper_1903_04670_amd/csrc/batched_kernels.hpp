@@ -93,10 +93,19 @@ __global__ void __launch_bounds__(128) kb_gain_yz(const SubItem *items, const in
   const SubItem &si = items[it];
   dispatch_N<NC>(si.N, [&](auto nn) {
     constexpr int NN = decltype(nn)::value;
-    const int jx = local % NN, r = (local / NN) % si.a.Nr, e = local / (NN * si.a.Nr);
     auto *lds = reinterpret_cast<C<T>(*)[NN][NN + 1]>(smem);
     // the phase rows follow the planes of the non-VSS body
     auto *phs = reinterpret_cast<C<T> *>(smem + (size_t)g_gain<NN>() * gain_bufs<T>() * NN * (NN + 1) * sizeof(C<T>));
+    if constexpr (gain_halves<T, NN>()) {
+      if (!si.vss && !si.a.pack) {
+        // two x-planes per block, one per wavefront (blocks_of counts N / 2)
+        const int w = threadIdx.x >> 6, jx = 2 * (local % (NN / 2)) + w;
+        const int r = (local / (NN / 2)) % si.a.Nr, e = local / ((NN / 2) * si.a.Nr);
+        gain_yz_halves_body<T, NN>(si.a, jx, r, e, threadIdx.x & 63, lds + gain_bufs<T>() * w, phs + w * 4 * NN);
+        return;
+      }
+    }
+    const int jx = local % NN, r = (local / NN) % si.a.Nr, e = local / (NN * si.a.Nr);
     if (si.vss) gain_yz_vss_body<T, NN, g_gain<NN>()>(si.a, jx, r, e, threadIdx.x, lds, phs);
     else if (si.a.pack) gain_yz_body<T, NN, packed_gain_groups<NN>(), 1, true>(si.a, jx, r, e, threadIdx.x, lds, phs);
     else gain_yz_body<T, NN, literal_gain_groups<T, NN>()>(si.a, jx, r, e, threadIdx.x, lds, phs);
@@ -136,7 +145,11 @@ static int blocks_of(int stage, const SubItem &s) {
   switch (stage) {
     case kFwd: return (N * s.fw.n_nodes * s.fw.nz + gs - 1) / gs;
     case kShift: return (s.a.pack && !s.vss ? (N * (N / 2) + 31) / 32 : pb) * 2 * E;
-    case kGainYZ: return N * s.a.Nr * E;
+    case kGainYZ: {
+      // the N = 32 literal body takes two x-planes per block
+      const bool halves = N == 32 && !s.vss && !s.a.pack;
+      return (halves ? N / 2 : N) * s.a.Nr * E;
+    }
     case kGainX: return s.vss ? pb * ((E + te - 1) / te) : pb * E;
     default: {
       const int gf = 128 / (2 * N) > 0 ? 128 / (2 * N) : 1;  // final_groups<N>()

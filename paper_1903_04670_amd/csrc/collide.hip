@@ -71,6 +71,8 @@ static hipError_t launch_pipeline_N(const PipeArgs &a, const FwdArgs &fw, const 
   if (!vss) {
     if (a.pack)
       DGFS_LAUNCH("k_gain_yz", (k_gain_yz<T, N, GP, 1, true>), dim3(N, a.Nr, EG), dim3(GP * 2 * N), 0, st, a);
+    else if constexpr (gain_halves<T, N>())
+      DGFS_LAUNCH("k_gain_yz", (k_gain_yz_halves<T, N>), dim3(N / 2, a.Nr, EG), dim3(128), 0, st, a);
     else
       DGFS_LAUNCH("k_gain_yz", (k_gain_yz<T, N, GG>), dim3(N, a.Nr, EG), dim3(GG * 2 * N), 0, st, a);
     if (sc.fuse)
@@ -178,6 +180,7 @@ void pipeline_slots(const dgfs_plan_s *pl, PipeArgs &a) {
   const bool share = symmetry_enabled();
   a.Mh = (int)pl->mhalf.size();
   a.mhalf = pl->mhalf_dev;
+  a.tinfo_half = pl->tinfo_half_dev;
   a.n_gslots = 0;
   for (int i = 0; i < a.n_pairs; ++i) a.cmirror[i] = -1;
   for (int i = 0; i < a.n_pairs; ++i) {
@@ -207,6 +210,7 @@ void pipeline_common(const dgfs_plan_s *pl, PipeArgs &a) {
   a.sidx = pl->sidx_dev;
   a.sx_zero = pl->sxz_dev;
   a.morder = pl->morder_dev;
+  a.tinfo_full = pl->tinfo_full_dev;
   a.sneg = pl->sneg_dev;
   a.gs_full = pl->gs_full_dev;
   a.gs_half = pl->gs_half_dev;

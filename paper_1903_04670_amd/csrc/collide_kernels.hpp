@@ -41,6 +41,9 @@ struct PipeArgs {
   const int *sidx;
   const int *sx_zero;  // [Sx]: 1 if that sigma_x value is zero (X then independent of r)
   const int *morder;   // [M]: directions in sigma_x-group order
+  // [M] and [Mh] groups of four ints in morder and mhalf order: m, s =
+  // sidx[m], sneg[s], sx_zero[s] | sx_zero[sneg[s]] << 1
+  const int *tinfo_full, *tinfo_half;
   const int *sneg;     // [Sx]: index of the opposite sigma_x value, or -1
   int xshare[kMaxPairs];  // 1: the pair has p == q on one input, so X2[s] = X1[sneg[s]]
   // Gain schedule.  The shift and gain kernels run over the n_gslots slots
@@ -182,6 +185,38 @@ __device__ __forceinline__ void col_phases_rec(cplx<T> (&h)[N / 2], const cplx<T
     else if (n > 0) phi = cmul(phi, rho);
     h[n] = cmul(h[n], phi);
   }
+}
+
+// Column phases of a whole column held by one lane (rows y < N), FP64, by
+// recurrence: consecutive rows differ by rho = ph(1) within each half of the
+// wave indices (y below N/2, y - N from N/2 on); the upper half restarts from
+// the table values ph(N/2) (possibly a zeroed Nyquist entry) and ph(N/2 + 1).
+// Requires N >= 4.
+template <typename T, int N>
+__device__ __forceinline__ void col_phases_full(cplx<T> (&h)[N], cplx<T> zph, cplx<T> rho, cplx<T> ph_half,
+                                                cplx<T> ph_half1) {
+  const cplx<T> q0 = cmul(zph, ph_half), q1 = cmul(zph, ph_half1);
+  cplx<T> phi = zph;
+#pragma unroll
+  for (int y = 0; y < N; ++y) {
+    if (y == N / 2) phi = q0;
+    else if (y == N / 2 + 1) phi = q1;
+    else if (y > 0) phi = cmul(phi, rho);
+    h[y] = cmul(h[y], phi);
+  }
+}
+
+// v_permlane32_swap on a 64-bit value in each operand: the upper half-wave
+// of a trades places with the lower half-wave of b, so lane l < 32 ends with
+// (a_l, a_{l+32}) and lane l + 32 with (b_l, b_{l+32}).  Every lane of the
+// wavefront must be active.
+__device__ __forceinline__ void half_swap(double &a, double &b) {
+  const unsigned long long ua = (unsigned long long)__double_as_longlong(a);
+  const unsigned long long ub = (unsigned long long)__double_as_longlong(b);
+  const auto lo = __builtin_amdgcn_permlane32_swap((unsigned)ua, (unsigned)ub, false, false);
+  const auto hi = __builtin_amdgcn_permlane32_swap((unsigned)(ua >> 32), (unsigned)(ub >> 32), false, false);
+  a = __longlong_as_double((long long)(((unsigned long long)hi[0] << 32) | lo[0]));
+  b = __longlong_as_double((long long)(((unsigned long long)hi[1] << 32) | lo[1]));
 }
 
 // Streaming store of one complex value: the x-shifted arrays and the C_r
@@ -352,6 +387,196 @@ template <typename T, int N> constexpr int literal_gain_groups() {
 // LDS of k_gain_yz besides its planes: per group the yz phase rows of its
 // current direction, [2 sides][2N] (y phases, then z phases).
 template <typename T, int N, int G> constexpr size_t gain_phase_elems() { return (size_t)G * 4 * N; }
+
+// The gain kernel's layout at N = 32 (gain_yz_halves_body): one wavefront
+// per (evaluation, r, x-plane), the two sides on its half-waves.
+template <typename T, int N> constexpr bool gain_halves() { return N == 32; }
+
+__device__ __forceinline__ void half_swap(float &a, float &b) {
+  const auto v = __builtin_amdgcn_permlane32_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+  a = __uint_as_float(v[0]);
+  b = __uint_as_float(v[1]);
+}
+
+// One (evaluation, r, x-plane) per wavefront at N = 32, with the two sides on
+// the two half-waves.  Lane (side, c), c < 32, holds a whole pencil: column
+// z = c for the y pass, row y = c for the z pass, so each transform runs
+// inside one lane, with no lane-pair exchange and no join twiddles that only
+// one lane of a pair needs.  After the row pass lane (0, c) holds u1 and lane
+// (1, c) holds u2 on row c; one half-wave swap per value leaves lane (h, c)
+// with both on z = 16 h + j, j < 16, where the product accumulates.  The
+// wavefront then takes the forward transform of its sum over lane pairs and
+// writes C_r.  Every direction of the slot is summed in one wavefront, in the
+// same order wherever this body runs, so results do not depend on the launch
+// (single plan or batch).
+//  * FP64: one LDS plane (pl[0]) carries one side's transpose at a time, so
+//    the registers of the other side's pencil stay untouched; the column
+//    phases come by recurrence from four table values.
+//  * FP32-mixed: one plane per side (pl[0], pl[1]), both sides transpose at
+//    once, and the column pass of a (sigma_x, sigma_y) class serves every
+//    direction of the class (the plan's term schedule); the z phase, constant
+//    along a column, is applied in the row pass.  Phase rows are staged in
+//    phs ([side][y row, z row]) one direction ahead, and the products are
+//    summed with compensation.
+template <typename T, int N>
+__device__ __forceinline__ void gain_yz_halves_body(const PipeArgs &a, int jx, int r, int e, int l,
+                                                    C<T> (*pl)[N][N + 1], C<T> *phs) {
+  static_assert(gain_halves<T, N>() && 2 * N == 64, "half-wave sides need N = 32");
+  constexpr int H = N / 2;
+  const int side = l >> 5, c = l & 31;
+  const int slot = e % a.n_pairs;
+  const PairDev pd = a.pairs[a.pair_id[slot]];
+  const size_t n3 = (size_t)N * N * N;
+  const C<T> *X = static_cast<const C<T> *>(a.X) + (size_t)e * 2 * a.Nr * a.Sx * n3;
+  const T *wm = static_cast<const T *>(a.wm);
+  const C<T> *pyz = static_cast<const C<T> *>(pd.pyz);
+  // the quadrature weight w_m (doubled on a half set) rides on side 0's z
+  // phase, which is constant along each column and enters u1 linearly
+  const T wscale = a.half[slot] ? (T)2 : (T)1;
+  C<T> P[H];
+#pragma unroll
+  for (int k = 0; k < H; ++k) P[k] = C<T>{0, 0};
+  if constexpr (sizeof(T) == 8) {
+    const int Mx = a.half[slot] ? a.Mh : a.M;
+    const int4 *tinfo = reinterpret_cast<const int4 *>(a.half[slot] ? a.tinfo_half : a.tinfo_full);
+    C<T>(*pw)[N + 1] = pl[0];
+    // Direction and x-shifted plane offsets of both sides for term mi (the
+    // choice of x_plane made with wave-uniform values), from one scalar load
+    // of the plan's term table, taken one term ahead.
+    auto term = [&](int mi, int &m, size_t &o0, size_t &o1) {
+      const int4 v = uload(tinfo, mi);
+      m = v.x;
+      const int s = v.y, sn = v.z;
+      const int rx = (v.w & 1) ? 0 : r;
+      o0 = ((size_t)rx * a.Sx + s) * n3;
+      if (a.xshare[slot] && sn >= 0) {
+        const int rxn = (v.w & 2) ? 0 : r;
+        o1 = ((size_t)rxn * a.Sx + sn) * n3;  // side 0's array of the opposite x component
+      } else {
+        o1 = (((size_t)a.Nr + rx) * a.Sx + s) * n3;
+      }
+    };
+    int m_n = 0;
+    size_t o0_n = 0, o1_n = 0;
+    if (Mx > 0) term(0, m_n, o0_n, o1_n);
+    for (int mi = 0; mi < Mx; ++mi) {
+      const int m = m_n;
+      const size_t o = side ? o1_n : o0_n;
+      if (mi + 1 < Mx) term(mi + 1, m_n, o0_n, o1_n);
+      // phase values first: the recurrence can start as the first rows arrive
+      const C<T> *ph = pyz + (((size_t)side * a.Nr + r) * a.M + m) * 2 * N;
+      const C<T> zph = gload(ph, N + c), rho = gload(ph, 1), phh = gload(ph, N / 2), phh1 = gload(ph, N / 2 + 1);
+      const C<T> *src = X + o + (size_t)jx * N * N + c;
+      C<T> h[N];
+#pragma unroll
+      for (int y = 0; y < N; ++y) h[y] = src[y * N];
+      const T ws = side ? (T)1 : uload(wm, m) * wscale;
+      col_phases_full<T, N>(h, cscale(zph, ws), rho, phh, phh1);
+      fft<N, +1>(h);
+      if (side == 0) {
+#pragma unroll
+        for (int y = 0; y < N; ++y) pw[y][c] = h[y];
+      }
+      group_sync<N>();
+      if (side == 0) {
+#pragma unroll
+        for (int z = 0; z < N; ++z) h[z] = pw[c][z];
+      }
+      group_sync<N>();
+      if (side == 1) {
+#pragma unroll
+        for (int y = 0; y < N; ++y) pw[y][c] = h[y];
+      }
+      group_sync<N>();
+      if (side == 1) {
+#pragma unroll
+        for (int z = 0; z < N; ++z) h[z] = pw[c][z];
+      }
+      group_sync<N>();
+      fft<N, +1>(h);
+#pragma unroll
+      for (int j = 0; j < H; ++j) {
+        half_swap(h[j].x, h[j + H].x);
+        half_swap(h[j].y, h[j + H].y);
+        // P += u1 u2 as two fused multiply-adds per component
+        P[j].x = __builtin_fma(h[j].x, h[j + H].x, __builtin_fma(-h[j].y, h[j + H].y, P[j].x));
+        P[j].y = __builtin_fma(h[j].x, h[j + H].y, __builtin_fma(h[j].y, h[j + H].x, P[j].y));
+      }
+    }
+  } else {
+    const int nT = a.half[slot] ? a.gs_T_half : a.gs_T_full;
+    const int *sch = a.half[slot] ? a.gs_half : a.gs_full;
+    T Pcx[H], Pcy[H];
+#pragma unroll
+    for (int k = 0; k < H; ++k) Pcx[k] = Pcy[k] = 0;
+    C<T> pf0{0, 0}, pf1{0, 0};
+    auto fetch_ph = [&](int m) {
+      pf0 = gload(pyz + ((size_t)r * a.M + m) * 2 * N, l);
+      pf1 = gload(pyz + (((size_t)a.Nr + r) * a.M + m) * 2 * N, l);
+    };
+    int ent_next = nT > 0 ? sch[0] : -1;
+    if (ent_next >= 0) fetch_ph(ent_next & 0xffff);
+    // schedule entries m | first << 16; a one-group schedule pads nothing
+    for (int t = 0; t < nT; ++t) {
+      const int ent = ent_next;
+      if (ent < 0) break;
+      ent_next = t + 1 < nT ? sch[t + 1] : -1;
+      const int m = ent & 0xffff;
+      const T ws = l >= N ? uload(wm, m) * wscale : (T)1;
+      phs[l] = C<T>{pf0.x * ws, pf0.y * ws};
+      phs[2 * N + l] = pf1;
+      group_sync<N>();
+      if (ent_next >= 0) fetch_ph(ent_next & 0xffff);
+      const C<T> *ph = phs + side * 2 * N;
+      if ((ent >> 16) & 1) {
+        const C<T> *src = x_plane(a, X, slot, side, r, a.sidx[m], n3) + (size_t)jx * N * N + c;
+        C<T> h[N];
+#pragma unroll
+        for (int y = 0; y < N; ++y) h[y] = cmul(src[y * N], ph[y]);
+        fft<N, +1>(h);
+#pragma unroll
+        for (int y = 0; y < N; ++y) pl[side][y][c] = h[y];
+        group_sync<N>();
+      }
+      C<T> h[N];
+#pragma unroll
+      for (int z = 0; z < N; ++z) h[z] = cmul(pl[side][c][z], ph[N + z]);
+      fft<N, +1>(h);
+#pragma unroll
+      for (int j = 0; j < H; ++j) {
+        half_swap(h[j].x, h[j + H].x);
+        half_swap(h[j].y, h[j + H].y);
+        const C<T> pr = cmul(h[j], h[j + H]);
+        acc_add(P[j].x, Pcx[j], pr.x);
+        acc_add(P[j].y, Pcy[j], pr.y);
+      }
+      group_sync<N>();
+    }
+#pragma unroll
+    for (int k = 0; k < H; ++k) P[k] = C<T>{P[k].x + Pcx[k], P[k].y + Pcy[k]};
+  }
+  // forward transform of the sum over lane pairs (cp, pp): z pass on row cp
+  // from the decimated columns 2n + pp, then y pass on column cp
+  C<T>(*pw)[N + 1] = pl[0];
+#pragma unroll
+  for (int k = 0; k < H; ++k) pw[c][side * H + k] = P[k];
+  group_sync<N>();
+  const int cp = l >> 1, pp = l & 1;
+  C<T> f[H];
+#pragma unroll
+  for (int n = 0; n < H; ++n) f[n] = pw[cp][2 * n + pp];
+  fft_pair<N, -1>(f, pp);
+  group_sync<N>();
+#pragma unroll
+  for (int k = 0; k < H; ++k) pw[cp][pp * H + k] = f[k];
+  group_sync<N>();
+#pragma unroll
+  for (int n = 0; n < H; ++n) f[n] = pw[2 * n + pp][cp];
+  fft_pair<N, -1>(f, pp);
+  C<T> *dst = static_cast<C<T> *>(a.Cb) + ((size_t)e * a.Nr + r) * n3 + (size_t)jx * N * N;
+#pragma unroll
+  for (int k = 0; k < H; ++k) store_stream(&dst[(pp * H + k) * N + cp], f[k]);
+}
 
 template <typename T, int N, int G, int NB = gain_bufs<T>(), bool PACK = false>
 __device__ __forceinline__ void gain_yz_body(const PipeArgs &a, int jx, int r, int e, int tid, C<T> (*lds)[N][N + 1],
@@ -664,6 +889,19 @@ __global__ void __launch_bounds__(G * 2 * N) k_gain_yz(PipeArgs a) {
   __shared__ C<T> lds[G * NB][N][N + 1];
   __shared__ C<T> phs[gain_phase_elems<T, N, G>()];
   gain_yz_body<T, N, G, NB, PACK>(a, blockIdx.x, blockIdx.y, gain_eval(a, blockIdx.z), threadIdx.x, lds, phs);
+}
+// Two x-planes per block, one per wavefront (gain_yz_halves_body); grid
+// (N / 2, N_rho, gain evaluations).  LDS per wavefront: one plane in FP64,
+// two planes and the staged phase rows in FP32 (the same layout as the
+// two-group k_gain_yz, which the batched kernel shares).
+template <typename T, int N>
+__global__ void __launch_bounds__(128) k_gain_yz_halves(PipeArgs a) {
+  constexpr int NB = gain_bufs<T>();
+  __shared__ C<T> lds[2 * NB][N][N + 1];
+  __shared__ C<T> phs[gain_phase_elems<T, N, 2>()];
+  const int w = threadIdx.x >> 6;
+  gain_yz_halves_body<T, N>(a, 2 * blockIdx.x + w, blockIdx.y, gain_eval(a, blockIdx.z), threadIdx.x & 63,
+                            lds + NB * w, phs + w * 4 * N);
 }
 
 // ------------------------------------------------------------------ k_gain_x

@@ -63,6 +63,10 @@ struct dgfs_plan_s {
   bool antipodal = false;
   std::vector<int> mhalf;
   const int *mhalf_dev = nullptr;      // [M/2] device copy of mhalf
+  // per-term index tables of the N = 32 gain kernel ([M] and [M/2] groups of
+  // four ints, in morder and mhalf order; see plan.cpp)
+  size_t tinfo_off = 0;
+  const int *tinfo_full_dev = nullptr, *tinfo_half_dev = nullptr;
   // gain-kernel term schedules with shared column passes, full and half sets
   int gs_T_full = 0, gs_T_half = 0;
   std::vector<int> gs_full, gs_half;

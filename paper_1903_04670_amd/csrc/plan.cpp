@@ -420,7 +420,12 @@ extern "C" dgfs_status dgfs_plan_create(const dgfs_params *prm, dgfs_plan *out) 
   }
   const int nsched = (int)pl->vjp_sched.size() + (int)pl->vjp_sched_sym.size();
   const int ngf = (int)pl->gs_full.size(), ngh = (int)pl->gs_half.size();
-  const size_t bytes_sidx = (((2 * M + 2 * pl->Sx + Mh + nsched + ngf + ngh) * sizeof(int) + 255) / 256) * 256;
+  // term tables of the N = 32 gain kernel: per direction of the full order
+  // (morder) and of the half set (mhalf), four ints: m, s = sidx[m],
+  // sneg[s], sx_zero[s] | sx_zero[sneg[s]] << 1
+  const int ntinfo = 4 * (M + Mh);
+  const size_t bytes_sidx =
+      (((2 * M + 2 * pl->Sx + Mh + nsched + ngf + ngh + 4 + ntinfo) * sizeof(int) + 255) / 256) * 256;
   pl->dev_bytes = bytes_vals + bytes_pairs + bytes_sidx;
   hipError_t he = hipMalloc(&pl->dev, pl->dev_bytes);
   if (he != hipSuccess) {
@@ -471,6 +476,17 @@ extern "C" dgfs_status dgfs_plan_create(const dgfs_params *prm, dgfs_plan *out) 
     if (ngh)
       std::memcpy(img.data() + bytes_vals + bytes_pairs + (2 * M + 2 * pl->Sx + Mh + nsched + ngf) * sizeof(int),
                   pl->gs_half.data(), ngh * sizeof(int));
+    // term tables, 16-byte aligned
+    const size_t t0 = ((2 * M + 2 * pl->Sx + Mh + nsched + ngf + ngh) + 3) / 4 * 4;
+    std::vector<int> tinfo;
+    auto add_term = [&](int m) {
+      const int sx = pl->sx_idx[m], sn = neg[sx];
+      tinfo.insert(tinfo.end(), {m, sx, sn, z[sx] | (sn >= 0 ? z[sn] : 0) << 1});
+    };
+    for (int m : order) add_term(m);
+    for (int m : pl->mhalf) add_term(m);
+    std::memcpy(img.data() + bytes_vals + bytes_pairs + t0 * sizeof(int), tinfo.data(), tinfo.size() * sizeof(int));
+    pl->tinfo_off = t0;
   }
   pl->pair_dev = reinterpret_cast<PairDev *>(base + bytes_vals);
   pl->wm_dev = base + off_wm * e;
@@ -483,6 +499,8 @@ extern "C" dgfs_status dgfs_plan_create(const dgfs_params *prm, dgfs_plan *out) 
   pl->vjp_sched_sym_dev = pl->vjp_sched_dev + pl->vjp_sched.size();
   pl->gs_full_dev = pl->vjp_sched_dev + nsched;
   pl->gs_half_dev = ngh ? pl->gs_full_dev + ngf : nullptr;
+  pl->tinfo_full_dev = pl->sidx_dev + pl->tinfo_off;
+  pl->tinfo_half_dev = Mh ? pl->tinfo_full_dev + 4 * M : nullptr;
   if (!pl->vhs) {
     dgfs_status vs = build_vss_tables(pl);
     if (vs != DGFS_OK) {

@@ -494,37 +494,55 @@ def collide_autograd(plan, p, q, fp, fq):
     return _CollideFn.get().apply(fp, fq, plan, p, q)
 
 
-def collide_batched(plans, items, accumulate=False, ws=None, stream=None):
-    """Heterogeneous batch in one launch per pipeline stage.
+class Batch:
+    """A heterogeneous batch whose descriptor array is built once.
 
     plans: list of Plan (same precision); items: list of
     (plan_index, p, q, fp, fq, out) with [n_nodes, N, N, N] float64 CUDA
-    tensors (node-strided views allowed)."""
-    torch = _torch()
-    handles = (ct.c_void_p * len(plans))(*[pl.handle for pl in plans])
-    arr = (Item * max(len(items), 1))()
-    for i, (k, p, q, fp, fq, out) in enumerate(items):
-        N = plans[k].N
-        if fp.dim() == 3:
-            fp, fq, out = fp[None], fq[None], out[None]
-        pf, sf = _node_view(fp, N)
-        pq_, sq = _node_view(fq, N)
-        po, so = _node_view(out, N)
-        if fp.shape[0] > 1 and sf != sq:
-            raise ValueError("item %d: fp and fq must share the node stride" % i)
-        arr[i] = Item(k, p, q, fp.shape[0], pf, pq_, sf, po, so)
-    n = len(items)
-    tensors = [t for it in items for t in it[3:6]]
-    with _Launch(stream, ws, *tensors) as run:
-        if ws is None:
-            nb = lib.dgfs_batched_workspace_bytes(handles, len(plans), arr, n)
-            if nb == 0 and n:
-                raise DGFSError(EINVAL, "dgfs_batched_workspace_bytes")
-            ws = torch.empty(max(nb, 256), dtype=torch.uint8, device="cuda")
-        _check(lib.dgfs_collide_batched(handles, len(plans), arr, n, ACCUMULATE if accumulate else 0,
-                                        ct.c_void_p(ws.data_ptr()), ws.numel(), run.ptr),
-               "dgfs_collide_batched")
-    return ws
+    tensors (node-strided views allowed).  The batch keeps references to the
+    plans and tensors; run() launches dgfs_collide_batched on the arrays as
+    they are at that time (one launch per pipeline stage per workspace
+    chunk)."""
+
+    def __init__(self, plans, items):
+        self.plans = list(plans)
+        self.items = list(items)
+        self.handles = (ct.c_void_p * len(self.plans))(*[pl.handle for pl in self.plans])
+        self.arr = (Item * max(len(self.items), 1))()
+        for i, (k, p, q, fp, fq, out) in enumerate(self.items):
+            N = self.plans[k].N
+            if fp.dim() == 3:
+                fp, fq, out = fp[None], fq[None], out[None]
+            pf, sf = _node_view(fp, N)
+            pq_, sq = _node_view(fq, N)
+            po, so = _node_view(out, N)
+            if fp.shape[0] > 1 and sf != sq:
+                raise ValueError("item %d: fp and fq must share the node stride" % i)
+            self.arr[i] = Item(k, p, q, fp.shape[0], pf, pq_, sf, po, so)
+        self.tensors = [t for it in self.items for t in it[3:6]]
+
+    def workspace_bytes(self):
+        nb = lib.dgfs_batched_workspace_bytes(self.handles, len(self.plans), self.arr, len(self.items))
+        if nb == 0 and self.items:
+            raise DGFSError(EINVAL, "dgfs_batched_workspace_bytes")
+        return max(nb, 256)
+
+    def run(self, accumulate=False, ws=None, stream=None):
+        """Launch the batch; returns the workspace used (allocated if None)."""
+        torch = _torch()
+        with _Launch(stream, ws, *self.tensors) as run:
+            if ws is None:
+                ws = torch.empty(self.workspace_bytes(), dtype=torch.uint8, device="cuda")
+            _check(lib.dgfs_collide_batched(self.handles, len(self.plans), self.arr, len(self.items),
+                                            ACCUMULATE if accumulate else 0, ct.c_void_p(ws.data_ptr()),
+                                            ws.numel(), run.ptr), "dgfs_collide_batched")
+        return ws
+
+
+def collide_batched(plans, items, accumulate=False, ws=None, stream=None):
+    """Heterogeneous batch in one launch per pipeline stage (see Batch);
+    returns the workspace used."""
+    return Batch(plans, items).run(accumulate=accumulate, ws=ws, stream=stream)
 
 
 def autotune(plan, p, q, fp, fq, out, ws=None, stream=None):

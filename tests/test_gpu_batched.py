@@ -162,3 +162,33 @@ def test_batched_accumulate_empty_items_and_strided_outputs(torch_cuda):
     torch.cuda.synchronize()
     for o, b in zip(outs_b, before):
         assert torch.equal(o, b)
+
+
+def test_prepared_batch_reruns_on_current_inputs(torch_cuda):
+    """dgfs.Batch builds its descriptor array once; run() twice, the inputs
+    overwritten in place between the runs: each run equals one dgfs_collide
+    call per item on the inputs of that time, bit for bit (the descriptors
+    hold addresses, not values).  An N = 32 FP64 item runs the half-wave gain
+    body, two x-planes per block, in both launches."""
+    from paper_1903_04670_amd import dgfs
+    torch = torch_cuda
+    insts = [small_config(8, ns=2, Nrho=3, seed=71, n_nodes=2),
+             small_config(32, ns=1, Nrho=2, seed=72, n_nodes=1),
+             small_config(16, ns=1, Nrho=3, seed=73, n_nodes=2, M_kind="octahedron")]
+    plans = [gpu_plan(cfg) for cfg in insts]
+    Fs = [torch.from_numpy(cfg["F"]).cuda() for cfg in insts]
+    items = []
+    for k, cfg in enumerate(insts):
+        for p in range(cfg["ns"]):
+            for q in range(cfg["ns"]):
+                items.append((k, p, q, Fs[k][:, p], Fs[k][:, q], torch.zeros_like(Fs[k][:, p])))
+    batch = dgfs.Batch(plans, items)
+    ws = batch.run()
+    for rerun in range(2):
+        if rerun:
+            for F in Fs:
+                F.mul_(0.5).add_(F.flip(-1), alpha=0.25)
+            batch.run(ws=ws)
+        torch.cuda.synchronize()
+        for (k, p, q, fp, fq, ob) in items:
+            assert torch.equal(ob, dgfs.collide(plans[k], p, q, fp, fq)), (rerun, k, p, q)

@@ -50,10 +50,7 @@ def test_rhs_2d_against_oracle(torch_cuda, Kx, Ky, P, periodic):
     mesh = dgfs.make_mesh2d(Kx, Ky, x=(0.0, 1.5), y=(-0.5, 0.5), periodic=periodic, walls=walls)
     F = torch.from_numpy(cfg["F"]).cuda()
     got = dgfs.rhs_2d(pl, F, mesh).cpu().numpy()
-    if Kx * Ky > 20:   # transport only for the long mesh (its collision term is the same kernel)
-        ref = box.transport_rhs(cfg["F"]) + mixture_collision(opl, cfg["F"])
-    else:
-        ref = box.rhs(cfg["F"], lambda G: mixture_collision(opl, G))
+    ref = box.rhs(cfg["F"], lambda G: mixture_collision(opl, G))
     assert rel_linf(got, ref) <= TOL
 
 
