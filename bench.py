@@ -51,6 +51,9 @@ def parse():
                          "schedule is reported")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device copy (reference for HBM byte counters)")
+    ap.add_argument("--no-nosym", action="store_true",
+                    help="skip the variant without the reuse of gain sums (its kernels carry the headline's "
+                         "names, so a profile of the other variants leaves it out)")
     return ap.parse_args()
 
 
@@ -182,8 +185,12 @@ def gain_roofline(cfg, r, tname, elt, steps, evals_per_step, gpp, gpq, gterms, p
     else:
         roof = {"bound": "alu", "achieved": round(tf, 2), "peak": peak_tflops, "unit": "TFLOP/s",
                 "frac": round(alu_frac, 4)}
-    groups = {("double", False): max(1, 128 // (2 * cfg["N"])), ("float", False): 1}
-    kname = "%s<%s, %d, %d, %d, false>" % (name, tname, cfg["N"], groups[(tname, False)], 1 if elt == 8 else 2)
+    if cfg["N"] == 32:
+        # one x-plane per wavefront, the two sides on its half-waves
+        kname = "k_gain_yz_halves<%s, 32>" % tname
+    else:
+        groups = {("double", False): max(1, 128 // (2 * cfg["N"])), ("float", False): 1}
+        kname = "%s<%s, %d, %d, %d, false>" % (name, tname, cfg["N"], groups[(tname, False)], 1 if elt == 8 else 2)
     roof.update({"traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                  "traffic": measured_traffic(kname), "kernel": kname, "avg_launch_ms": round(avg_ms, 4),
                  "evals_per_launch": evals_per_launch, "gain_slots_per_node": gpp + gpq,
@@ -204,8 +211,10 @@ def run(args):
     n_nodes = F0.shape[0]
     evals_per_step = 3 * n_nodes * cfg["ns"] ** 2
     out = {}
-    for prec, nyq, nosym in (("fp64", False, False), ("fp32", False, False), ("fp64", True, False),
-                             ("fp32", True, False), ("fp64", False, True)):
+    variants = [("fp64", False, False), ("fp32", False, False), ("fp64", True, False), ("fp32", True, False)]
+    if not args.no_nosym:
+        variants.append(("fp64", False, True))
+    for prec, nyq, nosym in variants:
         # the last variant turns the reuse of gain sums off (every ordered pair
         # sums over all M directions): the rate of a workload without the
         # symmetry of this one
@@ -545,7 +554,7 @@ def main():
               "MI355X; sharding across GPUs is described in the design notes, not implemented.", file=sys.stderr)
         sys.exit(2)
     cfg, evals_per_step, res = run(args)
-    r64, r32, rns = res["fp64"], res["fp32"], res["fp64_nosym"]
+    r64, r32, rns = res["fp64"], res["fp32"], res.get("fp64_nosym")
     n64, n32 = res["fp64_nyq"], res["fp32_nyq"]
     value = evals_per_step / (r64["ms"] / 1e3)
     gpp, gpq, gterms = gain_schedule(cfg)
@@ -597,7 +606,7 @@ def main():
             "fp64_TBps": round(value * model_bytes_per_eval(cfg["N"], cfg["M"], cfg["Nrho"], 8) / 1e12, 3),
             "fp32_mixed_TBps": round(value32 * model_bytes_per_eval(cfg["N"], cfg["M"], cfg["Nrho"], 4) / 1e12,
                                      3)},
-        "no_symmetry": {
+        "no_symmetry": None if rns is None else {
             "what": "FP64 step with the reuse of gain sums turned off: every ordered pair sums over all "
                     "M = 12 directions (48 direction terms per node instead of 24); the rate of a workload "
                     "without this one's antipodal sphere set and equal R_pq = R_qp",

@@ -96,19 +96,19 @@ __global__ void __launch_bounds__(128) kb_gain_yz(const SubItem *items, const in
     auto *lds = reinterpret_cast<C<T>(*)[NN][NN + 1]>(smem);
     // the phase rows follow the planes of the non-VSS body
     auto *phs = reinterpret_cast<C<T> *>(smem + (size_t)g_gain<NN>() * gain_bufs<T>() * NN * (NN + 1) * sizeof(C<T>));
-    if constexpr (gain_halves<T, NN>()) {
-      if (!si.vss && !si.a.pack) {
-        // two x-planes per block, one per wavefront (blocks_of counts N / 2)
-        const int w = threadIdx.x >> 6, jx = 2 * (local % (NN / 2)) + w;
-        const int r = (local / (NN / 2)) % si.a.Nr, e = local / ((NN / 2) * si.a.Nr);
-        gain_yz_halves_body<T, NN>(si.a, jx, r, e, threadIdx.x & 63, lds + gain_bufs<T>() * w, phs + w * 4 * NN);
-        return;
-      }
-    }
     const int jx = local % NN, r = (local / NN) % si.a.Nr, e = local / (NN * si.a.Nr);
-    if (si.vss) gain_yz_vss_body<T, NN, g_gain<NN>()>(si.a, jx, r, e, threadIdx.x, lds, phs);
-    else if (si.a.pack) gain_yz_body<T, NN, packed_gain_groups<NN>(), 1, true>(si.a, jx, r, e, threadIdx.x, lds, phs);
-    else gain_yz_body<T, NN, literal_gain_groups<T, NN>()>(si.a, jx, r, e, threadIdx.x, lds, phs);
+    if (si.vss) {
+      gain_yz_vss_body<T, NN, g_gain<NN>()>(si.a, jx, r, e, threadIdx.x, lds, phs);
+    } else if (si.a.pack) {
+      gain_yz_body<T, NN, packed_gain_groups<NN>(), 1, true>(si.a, jx, r, e, threadIdx.x, lds, phs);
+    } else if constexpr (gain_halves<T, NN>()) {
+      // two x-planes per block, one per wavefront (blocks_of counts N / 2)
+      const int w = threadIdx.x >> 6, jx2 = 2 * (local % (NN / 2)) + w;
+      const int r2 = (local / (NN / 2)) % si.a.Nr, e2 = local / ((NN / 2) * si.a.Nr);
+      gain_yz_halves_body<T, NN>(si.a, jx2, r2, e2, threadIdx.x & 63, lds + gain_bufs<T>() * w, phs + w * 4 * NN);
+    } else {
+      gain_yz_body<T, NN, literal_gain_groups<T, NN>()>(si.a, jx, r, e, threadIdx.x, lds, phs);
+    }
   });
 }
 

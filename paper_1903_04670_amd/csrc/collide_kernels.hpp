@@ -57,8 +57,8 @@ struct PipeArgs {
   int cmirror[kMaxPairs];  // the slot that reads this slot's C_r arrays, or -1
   int Mh;
   const int *mhalf;
-  // term schedules of the gain kernel with shared column passes ([G][T],
-  // entries m | first << 16 or -1), for the full and the half set
+  // FP32 term schedules of the N = 32 gain kernel with shared column passes
+  // (entries m | first << 16), for the full and the half set
   const int *gs_full, *gs_half;
   int gs_T_full, gs_T_half;
   // 1: the plan drops the Nyquist planes from the gain's translates (its
@@ -373,16 +373,13 @@ __global__ void __launch_bounds__(64) k_shift_x(PipeArgs a) {
 template <typename T> constexpr int gain_bufs() { return sizeof(T) == 4 ? 2 : 1; }
 
 // Groups per k_gain_yz block: at least 128 threads, except one wave per
-// block for the real-packed path at N = 32 and for the FP32 two-plane
-// kernel at N = 32 (measured faster: the block's final transform then idles
-// no second group).  The FP64 literal kernel keeps two (measured faster).
-// The batched kernel uses the same counts, so results match bit for bit,
-// and the plan builds the FP32 N = 32 term schedule for one group.
+// block for the real-packed path at N = 32 (measured faster: the block's
+// final transform then idles no second group).  The literal terms at N = 32
+// run gain_yz_halves_body instead.  The batched kernel uses the same counts,
+// so results match bit for bit.
 template <int N> constexpr int default_gain_groups() { return 128 / (2 * N) > 0 ? 128 / (2 * N) : 1; }
 template <int N> constexpr int packed_gain_groups() { return N == 32 ? 1 : default_gain_groups<N>(); }
-template <typename T, int N> constexpr int literal_gain_groups() {
-  return (sizeof(T) == 4 && N == 32) ? 1 : default_gain_groups<N>();
-}
+template <typename T, int N> constexpr int literal_gain_groups() { return default_gain_groups<N>(); }
 
 // LDS of k_gain_yz besides its planes: per group the yz phase rows of its
 // current direction, [2 sides][2N] (y phases, then z phases).
@@ -734,54 +731,6 @@ __device__ __forceinline__ void gain_yz_body(const PipeArgs &a, int jx, int r, i
       group_sync<N>();
       mi = mn;
       active = next;
-    }
-  } else if constexpr (NB == 2 && 2 * N == 64) {
-    // Terms from the plan's schedule: directions sharing (sigma_x, sigma_y)
-    // have the same y phases, and the z phase is constant along a column, so
-    // one column pass per side (y phases only) serves every direction of the
-    // class; each term's row passes apply its own z phases.
-    const int nT = a.half[slot] ? a.gs_T_half : a.gs_T_full;
-    const int *sch = (a.half[slot] ? a.gs_half : a.gs_full) + (size_t)(in_group ? g : 0) * nT;
-    int ent_next = (in_group && nT > 0) ? sch[0] : -1;
-    if (ent_next >= 0) fetch_ph(ent_next & 0xffff);
-    for (int t = 0; t < nT; ++t) {
-      const int ent = ent_next;
-      ent_next = (in_group && t + 1 < nT) ? sch[t + 1] : -1;
-      const bool active = ent >= 0;
-      const int m = active ? (ent & 0xffff) : 0;
-      if (active) stage_ph(m);
-      group_sync<N>();
-      if (ent_next >= 0) fetch_ph(ent_next & 0xffff);
-      if (active && ((ent >> 16) & 1)) {
-        const int s = a.sidx[m];
-#pragma unroll
-        for (int side = 0; side < 2; ++side) {
-          C<T> h[H];
-          load_col(side, s, h);
-          const C<T> *ph = phs + side * 2 * N;
-#pragma unroll
-          for (int n = 0; n < H; ++n) h[n] = cmul(h[n], ph[2 * n + p]);
-          fft_pair<N, +1>(h, p);
-#pragma unroll
-          for (int k = 0; k < H; ++k) lds[2 * g + side][p * H + k][c] = h[k];
-        }
-      }
-      group_sync<N>();
-      if (active) {
-        C<T> h[H];
-        const C<T> *zp0 = phs + N;
-#pragma unroll
-        for (int n = 0; n < H; ++n) h[n] = cmul(lds[2 * g][c][2 * n + p], zp0[2 * n + p]);
-        fft_pair<N, +1>(h, p);
-#pragma unroll
-        for (int k = 0; k < H; ++k) u1[k] = h[k];
-        const C<T> *zp1 = phs + 3 * N;
-#pragma unroll
-        for (int n = 0; n < H; ++n) h[n] = cmul(lds[2 * g + 1][c][2 * n + p], zp1[2 * n + p]);
-        fft_pair<N, +1>(h, p);
-        accumulate(h);
-      }
-      group_sync<N>();
     }
   } else {
   if (in_group && g < Mx) fetch_ph(mo[g]);

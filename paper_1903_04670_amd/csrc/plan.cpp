@@ -334,15 +334,14 @@ extern "C" dgfs_status dgfs_plan_create(const dgfs_params *prm, dgfs_plan *out) 
     }
   }
   const int Mh = (int)pl->mhalf.size();
-  // Gain-kernel term schedules for a block of G groups (FP32 at N = 32):
-  // directions sharing (sigma_x, sigma_y) share one column pass, so each
-  // group gets whole (sigma_x, sigma_y) classes (largest cost first onto the
-  // least loaded group); an entry is m | first << 16 (first: the column
-  // passes run before this term), padded with -1 to a common length T.
+  // FP32 term schedule of the N = 32 gain kernel (gain_yz_halves_body, one
+  // wavefront per x-plane): directions sharing (sigma_x, sigma_y) share one
+  // column pass, so they run as consecutive terms, largest class first; an
+  // entry is m | first << 16 (first: the column pass runs before this term).
+  // The table keeps the form of a schedule for G groups (one here), padded
+  // with -1 to a common length T.
   auto gain_sched = [&](const std::vector<int> &dirs, std::vector<int> &table) {
-    // the schedule serves the FP32 two-plane gain kernel at N = 32, which
-    // runs one group per block (literal_gain_groups)
-    const int G = N == 32 ? 1 : std::max(1, 128 / (2 * N));
+    const int G = 1;
     std::vector<std::vector<int>> classes;
     for (int m : dirs) {
       int found = -1;
