@@ -87,6 +87,32 @@ DGFS_HD cplx<T> twiddle(cplx<T> a) {
   }
 }
 
+template <typename T> DGFS_HD T fmaT(T a, T b, T c) {
+  if constexpr (sizeof(T) == 4) return __builtin_fmaf(a, b, c);
+  else return __builtin_fma(a, b, c);
+}
+
+// (a, b) <- (a + W_N^{DIR E} b, a - W_N^{DIR E} b).  With a general twiddle
+// the sum takes two fused multiply-adds per component and the difference
+// one more, as 2a - (a + W b): three instructions per component instead of a
+// twiddle product, an add and a subtract (four).
+template <int N, int DIR, int E, typename T>
+DGFS_HD void tw_butterfly(cplx<T> &a, cplx<T> &b) {
+  constexpr int e = ((E % N) + N) % N;
+  if constexpr (e == 0 || 4 * e == N || 2 * e == N || 4 * e == 3 * N) {
+    const cplx<T> t = twiddle<N, DIR, E>(b);
+    b = csub(a, t);
+    a = cadd(a, t);
+  } else {
+    constexpr ct::SC sc = ct::sincos2pi(e, N);
+    constexpr T c = (T)sc.c;
+    constexpr T s = (T)(DIR * sc.s);
+    const cplx<T> sum{fmaT(b.x, c, fmaT(-b.y, s, a.x)), fmaT(b.x, s, fmaT(b.y, c, a.y))};
+    b = cplx<T>{fmaT((T)2, a.x, -sum.x), fmaT((T)2, a.y, -sum.y)};
+    a = sum;
+  }
+}
+
 // ---------------------------------------------------------------- codelets
 template <int DIR, typename T>
 DGFS_HD void dft2(cplx<T>& a, cplx<T>& b) {
@@ -214,11 +240,30 @@ struct FFTView {
   static DGFS_HD void combine(cplx<T> (&x)[LEN]) {
     if constexpr (k1 < M) {
       cplx<T> y[R];
-      load_tw<0, k1, R, M>(x, y);
-      if constexpr (R == 2) dft2<DIR>(y[0], y[1]);
-      else if constexpr (R == 3) dft3<DIR>(y[0], y[1], y[2]);
-      else if constexpr (R == 4) dft4<DIR>(y[0], y[1], y[2], y[3]);
-      else dft_odd<R, DIR>(y);
+      if constexpr (R == 2) {
+        // the twiddle product feeds the butterfly (tw_butterfly)
+        y[0] = x[OFF + STRIDE * (2 * k1)];
+        y[1] = x[OFF + STRIDE * (1 + 2 * k1)];
+        tw_butterfly<N, DIR, k1>(y[0], y[1]);
+      } else if constexpr (R == 4) {
+        // dft4 of (y0, W^k1 y1, W^2k1 y2, W^3k1 y3) with the products of
+        // y2 and y3 fused into the butterflies that consume them
+        y[0] = x[OFF + STRIDE * (4 * k1)];
+        y[1] = twiddle<N, DIR, k1>(x[OFF + STRIDE * (1 + 4 * k1)]);
+        y[2] = x[OFF + STRIDE * (2 + 4 * k1)];
+        y[3] = x[OFF + STRIDE * (3 + 4 * k1)];
+        tw_butterfly<N, DIR, 2 * k1>(y[0], y[2]);  // a + c, a - c
+        tw_butterfly<N, DIR, 3 * k1>(y[1], y[3]);  // b + d, b - d
+        const cplx<T> s0 = y[0], s1 = y[2], s2 = y[1], s3 = mul_dir_i<DIR>(y[3]);
+        y[0] = cadd(s0, s2);
+        y[2] = csub(s0, s2);
+        y[1] = cadd(s1, s3);
+        y[3] = csub(s1, s3);
+      } else {
+        load_tw<0, k1, R, M>(x, y);
+        if constexpr (R == 3) dft3<DIR>(y[0], y[1], y[2]);
+        else dft_odd<R, DIR>(y);
+      }
       store_back<0, k1, R>(x, y);
       combine<k1 + 1, R, M>(x);
     }
