@@ -99,13 +99,16 @@ __global__ void __launch_bounds__(128) kb_gain_yz(const SubItem *items, const in
     const int jx = local % NN, r = (local / NN) % si.a.Nr, e = local / (NN * si.a.Nr);
     if (si.vss) {
       gain_yz_vss_body<T, NN, g_gain<NN>()>(si.a, jx, r, e, threadIdx.x, lds, phs);
-    } else if (si.a.pack) {
-      gain_yz_body<T, NN, packed_gain_groups<NN>(), 1, true>(si.a, jx, r, e, threadIdx.x, lds, phs);
     } else if constexpr (gain_halves<T, NN>()) {
       // two x-planes per block, one per wavefront (blocks_of counts N / 2)
       const int w = threadIdx.x >> 6, jx2 = 2 * (local % (NN / 2)) + w;
       const int r2 = (local / (NN / 2)) % si.a.Nr, e2 = local / ((NN / 2) * si.a.Nr);
-      gain_yz_halves_body<T, NN>(si.a, jx2, r2, e2, threadIdx.x & 63, lds + gain_bufs<T>() * w, phs + w * 4 * NN);
+      if (si.a.pack)
+        gain_yz_halves_packed_body<T, NN>(si.a, jx2, r2, e2, threadIdx.x & 63, lds + gain_bufs<T>() * w);
+      else
+        gain_yz_halves_body<T, NN>(si.a, jx2, r2, e2, threadIdx.x & 63, lds + gain_bufs<T>() * w, phs + w * 4 * NN);
+    } else if (si.a.pack) {
+      gain_yz_body<T, NN, packed_gain_groups<NN>(), 1, true>(si.a, jx, r, e, threadIdx.x, lds, phs);
     } else {
       gain_yz_body<T, NN, literal_gain_groups<T, NN>()>(si.a, jx, r, e, threadIdx.x, lds, phs);
     }
@@ -146,8 +149,8 @@ static int blocks_of(int stage, const SubItem &s) {
     case kFwd: return (N * s.fw.n_nodes * s.fw.nz + gs - 1) / gs;
     case kShift: return (s.a.pack && !s.vss ? (N * (N / 2) + 31) / 32 : pb) * 2 * E;
     case kGainYZ: {
-      // the N = 32 literal body takes two x-planes per block
-      const bool halves = N == 32 && !s.vss && !s.a.pack;
+      // the N = 32 bodies (literal and real-packed) take two x-planes per block
+      const bool halves = N == 32 && !s.vss;
       return (halves ? N / 2 : N) * s.a.Nr * E;
     }
     case kGainX: return s.vss ? pb * ((E + te - 1) / te) : pb * E;

@@ -69,12 +69,17 @@ static hipError_t launch_pipeline_N(const PipeArgs &a, const FwdArgs &fw, const 
   }
   constexpr int GG = literal_gain_groups<T, N>(), GP = packed_gain_groups<N>();
   if (!vss) {
-    if (a.pack)
-      DGFS_LAUNCH("k_gain_yz", (k_gain_yz<T, N, GP, 1, true>), dim3(N, a.Nr, EG), dim3(GP * 2 * N), 0, st, a);
-    else if constexpr (gain_halves<T, N>())
-      DGFS_LAUNCH("k_gain_yz", (k_gain_yz_halves<T, N>), dim3(N / 2, a.Nr, EG), dim3(128), 0, st, a);
-    else
-      DGFS_LAUNCH("k_gain_yz", (k_gain_yz<T, N, GG>), dim3(N, a.Nr, EG), dim3(GG * 2 * N), 0, st, a);
+    if constexpr (gain_halves<T, N>()) {
+      if (a.pack)
+        DGFS_LAUNCH("k_gain_yz", (k_gain_yz_halves_packed<T, N>), dim3(N / 2, a.Nr, EG), dim3(128), 0, st, a);
+      else
+        DGFS_LAUNCH("k_gain_yz", (k_gain_yz_halves<T, N>), dim3(N / 2, a.Nr, EG), dim3(128), 0, st, a);
+    } else {
+      if (a.pack)
+        DGFS_LAUNCH("k_gain_yz", (k_gain_yz<T, N, GP, 1, true>), dim3(N, a.Nr, EG), dim3(GP * 2 * N), 0, st, a);
+      else
+        DGFS_LAUNCH("k_gain_yz", (k_gain_yz<T, N, GG>), dim3(N, a.Nr, EG), dim3(GG * 2 * N), 0, st, a);
+    }
     if (sc.fuse)
       DGFS_LAUNCH("k_gain_x", (k_gain_x<T, N, true>), dim3(pb2, EG), dim3(64), 0, st, a);
     else

@@ -395,6 +395,36 @@ __device__ __forceinline__ void half_swap(float &a, float &b) {
   b = __uint_as_float(v[1]);
 }
 
+// Forward 2-D transform of a wavefront's sum over directions and the store
+// of C_r: lane (side, c) holds the sum on row c, z = side N/2 + k, k < N/2;
+// it goes through the plane, then lane pairs (cp, pp) take the z pass on row
+// cp from the decimated columns 2n + pp and the y pass on column cp.
+template <typename T, int N>
+__device__ __forceinline__ void halves_forward(const PipeArgs &a, int jx, int r, int e, int l, C<T> (*pw)[N + 1],
+                                               const C<T> (&P)[N / 2]) {
+  constexpr int H = N / 2;
+  const int side = l >> 5, c = l & 31;
+  const size_t n3 = (size_t)N * N * N;
+#pragma unroll
+  for (int k = 0; k < H; ++k) pw[c][side * H + k] = P[k];
+  group_sync<N>();
+  const int cp = l >> 1, pp = l & 1;
+  C<T> f[H];
+#pragma unroll
+  for (int n = 0; n < H; ++n) f[n] = pw[cp][2 * n + pp];
+  fft_pair<N, -1>(f, pp);
+  group_sync<N>();
+#pragma unroll
+  for (int k = 0; k < H; ++k) pw[cp][pp * H + k] = f[k];
+  group_sync<N>();
+#pragma unroll
+  for (int n = 0; n < H; ++n) f[n] = pw[2 * n + pp][cp];
+  fft_pair<N, -1>(f, pp);
+  C<T> *dst = static_cast<C<T> *>(a.Cb) + ((size_t)e * a.Nr + r) * n3 + (size_t)jx * N * N;
+#pragma unroll
+  for (int k = 0; k < H; ++k) store_stream(&dst[(pp * H + k) * N + cp], f[k]);
+}
+
 // One (evaluation, r, x-plane) per wavefront at N = 32, with the two sides on
 // the two half-waves.  Lane (side, c), c < 32, holds a whole pencil: column
 // z = c for the y pass, row y = c for the z pass, so each transform runs
@@ -552,27 +582,138 @@ __device__ __forceinline__ void gain_yz_halves_body(const PipeArgs &a, int jx, i
 #pragma unroll
     for (int k = 0; k < H; ++k) P[k] = C<T>{P[k].x + Pcx[k], P[k].y + Pcy[k]};
   }
-  // forward transform of the sum over lane pairs (cp, pp): z pass on row cp
-  // from the decimated columns 2n + pp, then y pass on column cp
+  halves_forward<T, N>(a, jx, r, e, l, pl[0], P);
+}
+
+// Real-packed terms (the Nyquist-zeroed variant) at N = 32, one wavefront per
+// (evaluation, r, x-plane): with the Nyquist planes dropped from both
+// translates, u1 and u2 are real, so one transform of h = t1 + i t2 gives
+// u1 = Re h and u2 = Im h (t1 carrying w_m), and the product is real.  Here
+// each half-wave takes its own direction term (directions 2i and 2i + 1 of
+// the slot), each lane a whole pencil of h: column z = c, then row y = c.
+// The x-shifted arrays hold the columns k_z < N/2 and are Hermitian (their
+// x-Nyquist plane is dropped too).  A lane of column c > N/2 reads column
+// N - c with rows in natural order, g(k') = X(k', N - c) = conj X(-k', c),
+// and transforms psi1 g1 - i psi2 g2 with psi(k') = conj(phi(-k')) (the z
+// phase conjugated; the y phase is unchanged away from the zeroed Nyquist
+// row): the result is the conjugate of the true column, so the row pass takes
+// conj of the entries k_z > N/2.  The lane of the Nyquist column reads column
+// 0, which its zero z phase discards.  A half-wave left without a direction
+// (odd counts) runs with zero phases.  After each pair of terms one half-wave
+// swap per value brings both halves' products of a point to one lane, which
+// sums them in the layout of halves_forward.
+template <typename T, int N>
+__device__ __forceinline__ void gain_yz_halves_packed_body(const PipeArgs &a, int jx, int r, int e, int l,
+                                                           C<T> (*pl)[N][N + 1]) {
+  static_assert(gain_halves<T, N>() && 2 * N == 64, "half-wave terms need N = 32");
+  constexpr int H = N / 2;
+  const int half = l >> 5, c = l & 31;
+  const int slot = e % a.n_pairs;
+  const PairDev pd = a.pairs[a.pair_id[slot]];
+  const size_t n3 = (size_t)N * N * N;
+  const C<T> *X = static_cast<const C<T> *>(a.X) + (size_t)e * 2 * a.Nr * a.Sx * n3;
+  const T *wm = static_cast<const T *>(a.wm);
+  const C<T> *pyz = static_cast<const C<T> *>(pd.pyz);
+  const T wscale = a.half[slot] ? (T)2 : (T)1;
+  const int Mx = a.half[slot] ? a.Mh : a.M;
+  const int4 *tinfo = reinterpret_cast<const int4 *>(a.half[slot] ? a.tinfo_half : a.tinfo_full);
+  const bool mr = c > H;
+  const int col = c < H ? c : (c == H ? 0 : N - c);
+  const T sg = mr ? (T)-1 : (T)1;  // sign of the i t2 term and of the z phase's imaginary part
   C<T>(*pw)[N + 1] = pl[0];
+  // sum over the slot's directions on row c, z = half N/2 + j
+  T P[H], Pc[sizeof(T) == 4 ? H : 1];
 #pragma unroll
-  for (int k = 0; k < H; ++k) pw[c][side * H + k] = P[k];
-  group_sync<N>();
-  const int cp = l >> 1, pp = l & 1;
-  C<T> f[H];
+  for (int k = 0; k < H; ++k) P[k] = 0;
+  if constexpr (sizeof(T) == 4) {
 #pragma unroll
-  for (int n = 0; n < H; ++n) f[n] = pw[cp][2 * n + pp];
-  fft_pair<N, -1>(f, pp);
-  group_sync<N>();
+    for (int k = 0; k < H; ++k) Pc[k] = 0;
+  }
+  for (int mi = 0; mi < Mx; mi += 2) {
+    const int my = mi + half;           // this half-wave's direction
+    const bool on = my < Mx;
+    const int4 v = uload(tinfo, on ? my : mi);
+    const int m = v.x, s = v.y, sn = v.z;
+    // x-shifted arrays of both sides (side 1 may use side 0's array of -s)
+    const int rx = (v.w & 1) ? 0 : r;
+    const size_t o0 = ((size_t)rx * a.Sx + s) * n3;
+    size_t o1;
+    if (a.xshare[slot] && sn >= 0) {
+      const int rxn = (v.w & 2) ? 0 : r;
+      o1 = ((size_t)rxn * a.Sx + sn) * n3;
+    } else {
+      o1 = (((size_t)a.Nr + rx) * a.Sx + s) * n3;
+    }
+    const C<T> *ph0 = pyz + ((size_t)r * a.M + m) * 2 * N;
+    const C<T> *ph1 = pyz + (((size_t)a.Nr + r) * a.M + m) * 2 * N;
+    const T ws = on ? gload(wm, m) * wscale : (T)0;
+    C<T> z0 = cscale(gload(ph0, N + c), ws), z1 = cscale(gload(ph1, N + c), on ? (T)1 : (T)0);
+    z0.y *= sg;
+    z1.y *= sg;
+    const C<T> rho0 = gload(ph0, 1), q00 = gload(ph0, N / 2), q01 = gload(ph0, N / 2 + 1);
+    const C<T> rho1 = gload(ph1, 1), q10 = gload(ph1, N / 2), q11 = gload(ph1, N / 2 + 1);
+    const C<T> *src0 = X + o0 + (size_t)jx * N * N + col;
+    const C<T> *src1 = X + o1 + (size_t)jx * N * N + col;
+    C<T> h[N];
 #pragma unroll
-  for (int k = 0; k < H; ++k) pw[cp][pp * H + k] = f[k];
-  group_sync<N>();
+    for (int y = 0; y < N; ++y) h[y] = src0[y * N];
+    col_phases_full<T, N>(h, z0, rho0, q00, q01);
+    // h += sg i phi1 X1, phi1 by the same recurrence, one row at a time
+    {
+      const C<T> a0 = cmul(z1, q10), a1 = cmul(z1, q11);
+      C<T> phi = z1;
 #pragma unroll
-  for (int n = 0; n < H; ++n) f[n] = pw[2 * n + pp][cp];
-  fft_pair<N, -1>(f, pp);
-  C<T> *dst = static_cast<C<T> *>(a.Cb) + ((size_t)e * a.Nr + r) * n3 + (size_t)jx * N * N;
+      for (int y = 0; y < N; ++y) {
+        if (y == N / 2) phi = a0;
+        else if (y == N / 2 + 1) phi = a1;
+        else if (y > 0) phi = cmul(phi, rho1);
+        const C<T> g = src1[y * N];
+        const C<T> t = cmul(g, phi);
+        h[y] = C<T>{fmaT(-sg, t.y, h[y].x), fmaT(sg, t.x, h[y].y)};
+      }
+    }
+    fft<N, +1>(h);
+    if (half == 0) {
 #pragma unroll
-  for (int k = 0; k < H; ++k) store_stream(&dst[(pp * H + k) * N + cp], f[k]);
+      for (int y = 0; y < N; ++y) pw[y][c] = h[y];
+    }
+    group_sync<N>();
+    if (half == 0) {
+#pragma unroll
+      for (int z = 0; z < N; ++z) h[z] = pw[c][z];
+    }
+    group_sync<N>();
+    if (half == 1) {
+#pragma unroll
+      for (int y = 0; y < N; ++y) pw[y][c] = h[y];
+    }
+    group_sync<N>();
+    if (half == 1) {
+#pragma unroll
+      for (int z = 0; z < N; ++z) h[z] = pw[c][z];
+    }
+    group_sync<N>();
+#pragma unroll
+    for (int z = H + 1; z < N; ++z) h[z].y = -h[z].y;  // mirrored columns
+    fft<N, +1>(h);
+    // products of both half-waves' directions on row c: one half-wave swap
+    // per value leaves lane (half, c) with both on z = half N/2 + j
+#pragma unroll
+    for (int j = 0; j < H; ++j) {
+      T lo = h[j].x * h[j].y, hi = h[j + H].x * h[j + H].y;
+      half_swap(lo, hi);
+      if constexpr (sizeof(T) == 4) {
+        acc_add(P[j], Pc[j], lo);
+        acc_add(P[j], Pc[j], hi);
+      } else {
+        P[j] += lo + hi;
+      }
+    }
+  }
+  C<T> S[H];
+#pragma unroll
+  for (int j = 0; j < H; ++j) S[j] = C<T>{sizeof(T) == 4 ? P[j] + Pc[j] : P[j], (T)0};
+  halves_forward<T, N>(a, jx, r, e, l, pw, S);
 }
 
 template <typename T, int N, int G, int NB = gain_bufs<T>(), bool PACK = false>
@@ -838,6 +979,16 @@ __global__ void __launch_bounds__(G * 2 * N) k_gain_yz(PipeArgs a) {
   __shared__ C<T> lds[G * NB][N][N + 1];
   __shared__ C<T> phs[gain_phase_elems<T, N, G>()];
   gain_yz_body<T, N, G, NB, PACK>(a, blockIdx.x, blockIdx.y, gain_eval(a, blockIdx.z), threadIdx.x, lds, phs);
+}
+// Real-packed terms: two x-planes per block, one per wavefront
+// (gain_yz_halves_packed_body, one LDS plane each); grid (N / 2, N_rho,
+// gain evaluations).
+template <typename T, int N>
+__global__ void __launch_bounds__(128) k_gain_yz_halves_packed(PipeArgs a) {
+  __shared__ C<T> lds[2][N][N + 1];
+  const int w = threadIdx.x >> 6;
+  gain_yz_halves_packed_body<T, N>(a, 2 * blockIdx.x + w, blockIdx.y, gain_eval(a, blockIdx.z), threadIdx.x & 63,
+                                   lds + w);
 }
 // Two x-planes per block, one per wavefront (gain_yz_halves_body); grid
 // (N / 2, N_rho, gain evaluations).  LDS per wavefront: one plane in FP64,
