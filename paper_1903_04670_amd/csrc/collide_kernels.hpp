@@ -359,6 +359,8 @@ __global__ void __launch_bounds__(64) k_shift_x(PipeArgs a) {
 }
 
 // ------------------------------------------------------------------ k_gain_yz
+// The paired-lane gain kernel, for N other than 32 (N = 32 runs
+// gain_yz_halves_body and gain_yz_halves_packed_body below).
 // Block = G groups of 2N threads on one (eval, r, x-plane); group g takes the
 // directions m = g, g+G, ...  Every length-N pencil is split over a lane pair
 // (fft_pair).  Per direction and side: the column (y) pass reads X coalesced

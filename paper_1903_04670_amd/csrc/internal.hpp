@@ -67,7 +67,8 @@ struct dgfs_plan_s {
   // four ints, in morder and mhalf order; see plan.cpp)
   size_t tinfo_off = 0;
   const int *tinfo_full_dev = nullptr, *tinfo_half_dev = nullptr;
-  // gain-kernel term schedules with shared column passes, full and half sets
+  // FP32 N = 32 gain-kernel term schedules with shared column passes, full
+  // and half sets
   int gs_T_full = 0, gs_T_half = 0;
   std::vector<int> gs_full, gs_half;
   const int *gs_full_dev = nullptr, *gs_half_dev = nullptr;
