@@ -224,6 +224,35 @@ def test_fp32_mixed_error_bound(torch_cuda):
         assert err_q <= 5e-4
 
 
+@pytest.mark.parametrize("kind", ["octahedron", "fibonacci"])
+def test_N32_other_sphere_sets(torch_cuda, kind):
+    """N = 32 runs the half-wave gain kernel.  The octahedron (its self
+    pairs sum over 3 antipodal representatives; the FP32 term schedule
+    shares one column pass between +-e_z) and a 7-point Fibonacci set (no
+    symmetry, 7 directions): all ordered pairs on two nodes in FP64 against
+    the oracle, and the cross and a self pair in FP32-mixed within the FP32
+    bounds (2e-6 of the loss term, 5e-4 of Q)."""
+    from oracle.collide import collide_gain_loss
+    cfg = small_config(32, ns=2, M_kind=kind, Nrho=2, seed=91, n_nodes=2)
+    opl = oracle_pairs(cfg)
+    pl = gpu_plan(cfg)
+    for p in range(2):
+        for q in range(2):
+            got = run_gpu(torch_cuda, pl, cfg["F"], p, q)
+            for i in range(cfg["n_nodes"]):
+                ref = oracle_collide(opl[p][q], cfg["F"][i, p], cfg["F"][i, q])
+                assert rel_linf(got[i], ref) <= TOL, (kind, p, q, i)
+    pl32 = gpu_plan(cfg, precision="fp32")
+    for p, q in [(0, 1), (1, 1)]:
+        got = run_gpu(torch_cuda, pl32, cfg["F"], p, q)
+        gain, loss = collide_gain_loss(opl[p][q], cfg["F"][0, p], cfg["F"][0, q])
+        ref = gain - loss
+        err_q = rel_linf(got[0], ref)
+        err_l = float(np.max(np.abs(got[0] - ref)) / np.max(np.abs(loss)))
+        assert err_l <= 2e-6, (kind, p, q, err_l)
+        assert err_q <= 5e-4, (kind, p, q, err_q)
+
+
 @pytest.mark.parametrize("N", [40, 56])
 def test_fp32_mixed_radix5_radix7_grids(torch_cuda, N):
     """FP32-mixed plans on N = 40 and 56 (radix-5 and radix-7 transforms in

@@ -56,6 +56,24 @@ def test_packed_gain_small_sizes_all_pairs(torch_cuda, N, kind):
             assert rel_linf(got[0], ref0) > 10 * TOL, (N, p, q)
 
 
+@pytest.mark.parametrize("kind", ["octahedron", "fibonacci"])
+def test_packed_gain_N32_odd_direction_counts(torch_cuda, kind):
+    """N = 32 runs the half-wave real-packed kernel, which gives a direction
+    term to each half-wave: the octahedron's self pairs sum over 3
+    representatives and a 7-point Fibonacci set (not antipodal) over all 7
+    directions, so one half-wave runs without a direction in the last pair
+    of terms.  All ordered pairs, two nodes, against the oracle's variant."""
+    cfg = small_config(32, ns=2, M_kind=kind, Nrho=2, seed=66, n_nodes=2)
+    opl = oracle_pairs(cfg, nyquist_zero=True)
+    pl = gpu_plan(cfg, nyquist_zero=True)
+    for p in range(2):
+        for q in range(2):
+            got = _collide(torch_cuda, pl, cfg["F"], p, q)
+            for i in range(cfg["n_nodes"]):
+                ref = oracle_collide(opl[p][q], cfg["F"][i, p], cfg["F"][i, q])
+                assert rel_linf(got[i], ref) <= TOL, (kind, p, q, i)
+
+
 def test_packed_gain_couette_N32_all_pairs(torch_cuda):
     """N = 32, icosahedron M = 12, N_rho = 16, two species, one node."""
     cfg = wl.couette_two_species(K=1, P=0)
