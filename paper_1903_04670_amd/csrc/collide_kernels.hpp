@@ -251,11 +251,11 @@ template <typename T> __device__ __forceinline__ void acc_add(T &s, T &c, T x) {
 template <typename T>
 __device__ __forceinline__ const C<T> *x_plane(const PipeArgs &a, const C<T> *Xe, int slot, int side, int r,
                                                int s, size_t n3) {
-  if (side == 1 && a.xshare[slot] && a.sneg[s] >= 0) {
+  if (side == 1 && a.xshare[slot] && uload(a.sneg, s) >= 0) {
     side = 0;
-    s = a.sneg[s];
+    s = uload(a.sneg, s);
   }
-  const int rx = a.sx_zero[s] ? 0 : r;  // X of a zero x-component does not depend on r
+  const int rx = uload(a.sx_zero, s) ? 0 : r;  // X of a zero x-component does not depend on r
   return Xe + (((size_t)side * a.Nr + rx) * a.Sx + s) * n3;
 }
 
@@ -335,8 +335,10 @@ __device__ __forceinline__ void shift_x_body(const PipeArgs &a, int bx, int side
   const int nrs = a.Nr * a.Sx, rs_per = (nrs + nparts - 1) / nparts;
   const int rs_end = min(nrs, (part + 1) * rs_per);
   for (int rs = part * rs_per; rs < rs_end; ++rs) {
-    if (rs >= a.Sx && a.sx_zero[rs % a.Sx]) continue;
-    if (shared && a.sneg[rs % a.Sx] >= 0) continue;
+    // plan tables through the scalar cache: a vector load here would put a
+    // memory round trip before every (r, s) array
+    if (rs >= a.Sx && uload(a.sx_zero, rs % a.Sx)) continue;
+    if (shared && uload(a.sneg, rs % a.Sx) >= 0) continue;
     const C<T> *ph = px + (size_t)rs * N + p * H;
     C<T> w[H];
 #pragma unroll
@@ -543,13 +545,13 @@ __device__ __forceinline__ void gain_yz_halves_body(const PipeArgs &a, int jx, i
       pf0 = gload(pyz + ((size_t)r * a.M + m) * 2 * N, l);
       pf1 = gload(pyz + (((size_t)a.Nr + r) * a.M + m) * 2 * N, l);
     };
-    int ent_next = nT > 0 ? sch[0] : -1;
+    int ent_next = nT > 0 ? uload(sch, 0) : -1;
     if (ent_next >= 0) fetch_ph(ent_next & 0xffff);
     // schedule entries m | first << 16; a one-group schedule pads nothing
     for (int t = 0; t < nT; ++t) {
       const int ent = ent_next;
       if (ent < 0) break;
-      ent_next = t + 1 < nT ? sch[t + 1] : -1;
+      ent_next = t + 1 < nT ? uload(sch, t + 1) : -1;
       const int m = ent & 0xffff;
       const T ws = l >= N ? uload(wm, m) * wscale : (T)1;
       phs[l] = C<T>{pf0.x * ws, pf0.y * ws};
@@ -558,7 +560,7 @@ __device__ __forceinline__ void gain_yz_halves_body(const PipeArgs &a, int jx, i
       if (ent_next >= 0) fetch_ph(ent_next & 0xffff);
       const C<T> *ph = phs + side * 2 * N;
       if ((ent >> 16) & 1) {
-        const C<T> *src = x_plane(a, X, slot, side, r, a.sidx[m], n3) + (size_t)jx * N * N + c;
+        const C<T> *src = x_plane(a, X, slot, side, r, uload(a.sidx, m), n3) + (size_t)jx * N * N + c;
         C<T> h[N];
 #pragma unroll
         for (int y = 0; y < N; ++y) h[y] = cmul(src[y * N], ph[y]);
@@ -825,17 +827,19 @@ __device__ __forceinline__ void gain_yz_body(const PipeArgs &a, int jx, int r, i
         h[n] = C<T>{v.x, csg * v.y};
       }
     };
-    int mi = g;
+    // with one group per block the direction index is the same in every
+    // lane, so the plan tables and x_plane are read through the scalar cache
+    int mi = G == 1 ? 0 : g;
     bool active = in_group && mi < Mx;
     if (active) {
-      fetch_ph(mo[mi]);
-      stage_ph(mo[mi]);
-      if (mi + G < Mx) fetch_ph(mo[mi + G]);
+      fetch_ph(uload(mo, mi));
+      stage_ph(uload(mo, mi));
+      if (mi + G < Mx) fetch_ph(uload(mo, mi + G));
     }
     group_sync<N>();
     for (int it = 0; it < iters; ++it) {
       if (active) {
-        const int s = a.sidx[mo[mi]];
+        const int s = uload(a.sidx, uload(mo, mi));
         C<T> h[H], h1[H];
         load_half(0, s, h);
         load_half(1, s, h1);
@@ -854,8 +858,8 @@ __device__ __forceinline__ void gain_yz_body(const PipeArgs &a, int jx, int r, i
       const int mn = mi + G;
       const bool next = in_group && mn < Mx;
       if (next) {
-        stage_ph(mo[mn]);
-        if (mn + G < Mx) fetch_ph(mo[mn + G]);
+        stage_ph(uload(mo, mn));
+        if (mn + G < Mx) fetch_ph(uload(mo, mn + G));
       }
       if (active) {
         C<T> h[H];
@@ -876,15 +880,19 @@ __device__ __forceinline__ void gain_yz_body(const PipeArgs &a, int jx, int r, i
       active = next;
     }
   } else {
-  if (in_group && g < Mx) fetch_ph(mo[g]);
+  // with one group per block the direction index is the same in every lane
+  // (lanes outside the group only skip the work), so the plan tables and
+  // x_plane are read through the scalar cache
+  const int g0 = G == 1 ? 0 : g;
+  if (in_group && g0 < Mx) fetch_ph(uload(mo, g0));
   for (int it = 0; it < iters; ++it) {
-    const int mi = it * G + g;
+    const int mi = it * G + g0;
     const bool active = in_group && mi < Mx;
-    const int m = active ? mo[mi] : 0;
-    const int s = a.sidx[m];
+    const int m = mi < Mx ? uload(mo, mi) : 0;
+    const int s = uload(a.sidx, m);
     if (active) stage_ph(m);
     group_sync<N>();
-    if (active && mi + G < Mx) fetch_ph(mo[mi + G]);
+    if (active && mi + G < Mx) fetch_ph(uload(mo, mi + G));
     if constexpr (NB == 2) {
       if (active) {
         col_pass(0, m, s, lds[2 * g]);

@@ -191,11 +191,11 @@ __global__ void __launch_bounds__(G * 2 * N) k_vjp_yz(VjpArgs v) {
   for (int k = 0; k < H; ++k) acc[k] = C<T>{0, 0};
   const int *sched = v.sched + (in_group ? g : 0) * v.sched_T;
   for (int t = 0; t < v.sched_T; ++t) {
-    const int ent = in_group ? sched[t] : -1;
+    const int ent = in_group ? uload(sched, t) : -1;
     const bool active = ent >= 0;
     const int m = active ? (ent & 0xffff) : 0;
     const int side = (ent >> 16) & 1, uside = 1 - side;
-    const int s = a.sidx[m];
+    const int s = uload(a.sidx, m);
     if constexpr (VSS) form_v(active, ((size_t)e * a.Nr + r) * a.M + m);
     if (active) {
       const C<T> *src = x_plane(a, X, slot, uside, r, s, n3) + (size_t)jx * N * N;

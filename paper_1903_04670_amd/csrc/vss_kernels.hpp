@@ -36,19 +36,23 @@ __device__ __forceinline__ void gain_yz_vss_body(const PipeArgs &a, int jx, int 
     pf0 = gload(pyz + ((size_t)r * a.M + m) * 2 * N, l);
     pf1 = gload(pyz + (((size_t)a.Nr + r) * a.M + m) * 2 * N, l);
   };
-  if (in_group && g < a.M) fetch_ph(a.morder[g]);
+  // with one group per block the direction index is the same in every lane
+  // (lanes outside the group only skip the work), so the plan tables and
+  // x_plane are read through the scalar cache
+  const int g0 = G == 1 ? 0 : g;
+  if (in_group && g0 < a.M) fetch_ph(uload(a.morder, g0));
   const int iters = (a.M + G - 1) / G;
   for (int it = 0; it < iters; ++it) {
-    const int mi = it * G + g;
+    const int mi = it * G + g0;
     const bool active = in_group && mi < a.M;
-    const int m = active ? a.morder[mi] : 0;
-    const int s = a.sidx[m];
+    const int m = mi < a.M ? uload(a.morder, mi) : 0;
+    const int s = uload(a.sidx, m);
     if (active) {
       phs[l] = pf0;
       phs[2 * N + l] = pf1;
     }
     group_sync<N>();
-    if (active && mi + G < a.M) fetch_ph(a.morder[mi + G]);
+    if (active && mi + G < a.M) fetch_ph(uload(a.morder, mi + G));
 #pragma unroll 1
     for (int side = 0; side < 2; ++side) {
       if (active) {
