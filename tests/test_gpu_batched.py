@@ -23,7 +23,7 @@ def _run(torch, insts, precision):
     from paper_1903_04670_amd import dgfs
     plans, items, outs_b, outs_s, tensors = [], [], [], [], []
     for k, cfg in enumerate(insts):
-        pl = gpu_plan(cfg, precision=precision)
+        pl = gpu_plan(cfg, precision=precision, nyquist_zero=cfg.get("nyquist_zero", False))
         plans.append(pl)
         F = torch.from_numpy(cfg["F"]).cuda()
         tensors.append(F)
@@ -124,6 +124,24 @@ def test_batched_radix5_radix7_grids_equal_single_calls(torch_cuda, precision):
         ref = oracle_collide(oracle_pairs(cfg)[0][0], cfg["F"][0, 0], cfg["F"][0, 0])
         got = [ob for (k, p, q, _, _, ob) in items if k == 3][0].cpu().numpy()[0]
         assert rel_linf(got, ref) <= 1e-11
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_batched_one_group_blocks_vss_and_packed_equal_single_calls(torch_cuda, precision):
+    """Above N = 32 a gain block is one group of 2N lanes, and the batched
+    launch's 128-thread blocks carry lanes outside it: a VSS item (alpha =
+    1.3, Fibonacci M = 7) and a Nyquist-zeroed item on N = 40, with an N = 12
+    item, in one batched launch per stage give bit for bit the single-plan
+    results."""
+    torch = torch_cuda
+    vss = small_config(40, ns=1, M_kind="fibonacci", Nrho=2, seed=95, n_nodes=1)
+    vss["alpha"] = np.full((1, 1), 1.3)
+    nyq = small_config(40, ns=2, M_kind="octahedron", Nrho=2, seed=96, n_nodes=1)
+    nyq["nyquist_zero"] = True
+    insts = [small_config(12, ns=1, Nrho=3, seed=97, n_nodes=2), vss, nyq]
+    plans, items, outs_b, outs_s = _run(torch, insts, precision)
+    for ob, os_ in zip(outs_b, outs_s):
+        assert torch.equal(ob, os_)
 
 
 def test_batched_accumulate_empty_items_and_strided_outputs(torch_cuda):
