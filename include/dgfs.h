@@ -105,8 +105,9 @@ typedef enum { DGFS_OP_COLLIDE = 0, DGFS_OP_VJP = 1, DGFS_OP_RHS = 2, DGFS_OP_ST
  *   N_rho          Gauss-Legendre points on [0, R] (the radial rule)
  *   dg_order       DG polynomial degree P (P+1 Gauss-Lobatto nodes per
  *                  element); only used by dgfs_rhs/dgfs_step, 0 otherwise
- *   precision      DGFS_FP64, or DGFS_FP32_MIXED (FP32 transforms with
- *                  compensated FP32 accumulation; inputs/outputs stay FP64)
+ *   precision      DGFS_FP64, or DGFS_FP32_MIXED (FP32 transforms; the
+ *                  sums over directions and radii compensated in FP32 or
+ *                  carried in FP64; inputs/outputs stay FP64)
  *   nyquist_zero   0: Algorithm 2 as it stands.  1: the gain's translates
  *                  t1, t2 are formed from fft(f^p), fft(f^q) with their
  *                  Nyquist planes (wave index -N/2 on any axis) set to zero;

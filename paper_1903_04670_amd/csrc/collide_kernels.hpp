@@ -447,8 +447,8 @@ __device__ __forceinline__ void halves_forward(const PipeArgs &a, int jx, int r,
 //    once, and the column pass of a (sigma_x, sigma_y) class serves every
 //    direction of the class (the plan's term schedule); the z phase, constant
 //    along a column, is applied in the row pass.  Phase rows are staged in
-//    phs ([side][y row, z row]) one direction ahead, and the products are
-//    summed with compensation.
+//    phs ([side][y row, z row]) one direction ahead, and the products, exact
+//    in FP64, are summed in FP64.
 template <typename T, int N>
 __device__ __forceinline__ void gain_yz_halves_body(const PipeArgs &a, int jx, int r, int e, int l,
                                                     C<T> (*pl)[N][N + 1], C<T> *phs) {
@@ -537,9 +537,12 @@ __device__ __forceinline__ void gain_yz_halves_body(const PipeArgs &a, int jx, i
   } else {
     const int nT = a.half[slot] ? a.gs_T_half : a.gs_T_full;
     const int *sch = a.half[slot] ? a.gs_half : a.gs_full;
-    T Pcx[H], Pcy[H];
+    // the product of two FP32 values is exact in FP64, and the sum over
+    // directions runs in FP64 (as many registers as an FP32 sum with its
+    // compensation, and fewer instructions)
+    double Px[H], Py[H];
 #pragma unroll
-    for (int k = 0; k < H; ++k) Pcx[k] = Pcy[k] = 0;
+    for (int k = 0; k < H; ++k) Px[k] = Py[k] = 0.0;
     C<T> pf0{0, 0}, pf1{0, 0};
     auto fetch_ph = [&](int m) {
       pf0 = gload(pyz + ((size_t)r * a.M + m) * 2 * N, l);
@@ -577,14 +580,14 @@ __device__ __forceinline__ void gain_yz_halves_body(const PipeArgs &a, int jx, i
       for (int j = 0; j < H; ++j) {
         half_swap(h[j].x, h[j + H].x);
         half_swap(h[j].y, h[j + H].y);
-        const C<T> pr = cmul(h[j], h[j + H]);
-        acc_add(P[j].x, Pcx[j], pr.x);
-        acc_add(P[j].y, Pcy[j], pr.y);
+        const double ax = h[j].x, ay = h[j].y, bx = h[j + H].x, by = h[j + H].y;
+        Px[j] = __builtin_fma(ax, bx, __builtin_fma(-ay, by, Px[j]));
+        Py[j] = __builtin_fma(ax, by, __builtin_fma(ay, bx, Py[j]));
       }
       group_sync<N>();
     }
 #pragma unroll
-    for (int k = 0; k < H; ++k) P[k] = C<T>{P[k].x + Pcx[k], P[k].y + Pcy[k]};
+    for (int k = 0; k < H; ++k) P[k] = C<T>{(T)Px[k], (T)Py[k]};
   }
   halves_forward<T, N>(a, jx, r, e, l, pl[0], P);
 }
