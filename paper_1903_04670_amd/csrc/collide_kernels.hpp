@@ -230,7 +230,7 @@ template <typename T> __device__ __forceinline__ void store_stream(cplx<T> *dst,
   __builtin_nontemporal_store(w, reinterpret_cast<V2 *>(dst));
 }
 
-// Compensated accumulation (used by the FP32 path): Kahan's summation with
+// Compensated accumulation (the FP32 paired-lane gain and x kernels): Kahan's summation with
 // the correction kept so that s + c is the running sum.  The rounding error
 // of each addition, y - (t - s), is recovered exactly and fed into the next
 // one; the error of the total is bounded by about 2 eps sum |x_i|,
@@ -628,14 +628,11 @@ __device__ __forceinline__ void gain_yz_halves_packed_body(const PipeArgs &a, in
   const int col = c < H ? c : (c == H ? 0 : N - c);
   const T sg = mr ? (T)-1 : (T)1;  // sign of the i t2 term and of the z phase's imaginary part
   C<T>(*pw)[N + 1] = pl[0];
-  // sum over the slot's directions on row c, z = half N/2 + j
-  T P[H], Pc[sizeof(T) == 4 ? H : 1];
+  // sum over the slot's directions on row c, z = half N/2 + j, in FP64 in
+  // both precisions (in FP32 as many registers as a compensated sum)
+  double P[H];
 #pragma unroll
-  for (int k = 0; k < H; ++k) P[k] = 0;
-  if constexpr (sizeof(T) == 4) {
-#pragma unroll
-    for (int k = 0; k < H; ++k) Pc[k] = 0;
-  }
+  for (int k = 0; k < H; ++k) P[k] = 0.0;
   for (int mi = 0; mi < Mx; mi += 2) {
     const int my = mi + half;           // this half-wave's direction
     const bool on = my < Mx;
@@ -710,8 +707,8 @@ __device__ __forceinline__ void gain_yz_halves_packed_body(const PipeArgs &a, in
       T lo = h[j].x * h[j].y, hi = h[j + H].x * h[j + H].y;
       half_swap(lo, hi);
       if constexpr (sizeof(T) == 4) {
-        acc_add(P[j], Pc[j], lo);
-        acc_add(P[j], Pc[j], hi);
+        P[j] += (double)lo;
+        P[j] += (double)hi;
       } else {
         P[j] += lo + hi;
       }
@@ -719,7 +716,7 @@ __device__ __forceinline__ void gain_yz_halves_packed_body(const PipeArgs &a, in
   }
   C<T> S[H];
 #pragma unroll
-  for (int j = 0; j < H; ++j) S[j] = C<T>{sizeof(T) == 4 ? P[j] + Pc[j] : P[j], (T)0};
+  for (int j = 0; j < H; ++j) S[j] = C<T>{(T)P[j], (T)0};
   halves_forward<T, N>(a, jx, r, e, l, pw, S);
 }
 

@@ -5,7 +5,7 @@
 //   k_gain_yz_vss : per (eval, r, x-plane) and direction m: u1, u2 (as the VHS
 //                   kernel), the product, and its forward yz transform C_rm
 //   k_gain_x_vss  : per x-line: QG = sum_{r,m} B_rm(k) FFT_x C_rm with
-//                   B_rm = w_r w_m b_rm / N^3 (compensated in FP32), then
+//                   B_rm = w_r w_m b_rm / N^3 (summed in FP64), then
 //                   V1 = iFFT_x QG and V2 = iFFT_x(c FFT_x Z_q).  A thread pair
 //                   serves TE nodes of the same ordered pair so each table
 //                   x-line is read once per TE evaluations.
@@ -126,15 +126,13 @@ __device__ __forceinline__ void gain_x_vss_body(const PipeArgs &a, int bx, int b
   const size_t n3 = (size_t)N * N * N;
   const int vy = wave_idx(pc / N, N), vz = wave_idx(pc % N, N), kyz = vy * vy + vz * vz;
   const C<T> *B = static_cast<const C<T> *>(pd.btab);
-  C<T> Q[TE][H];
-  T Qcx[TE][sizeof(T) == 4 ? H : 1], Qcy[TE][sizeof(T) == 4 ? H : 1];
+  // QG in FP64 in both precisions: in FP32 each table value and transform
+  // are widened and their product fused-multiply-added
+  C<double> Q[TE][H];
 #pragma unroll
   for (int j = 0; j < TE; ++j)
 #pragma unroll
-    for (int k = 0; k < H; ++k) {
-      Q[j][k] = C<T>{0, 0};
-      if constexpr (sizeof(T) == 4) Qcx[j][k] = Qcy[j][k] = 0;
-    }
+    for (int k = 0; k < H; ++k) Q[j][k] = C<double>{0, 0};
   for (int rm = 0; rm < a.Nr * a.M; ++rm) {
     C<T> b[H];
     const C<T> *bl = B + (size_t)rm * n3;
@@ -151,11 +149,12 @@ __device__ __forceinline__ void gain_x_vss_body(const PipeArgs &a, int bx, int b
       fft_pair<N, -1>(w, p);
 #pragma unroll
       for (int k = 0; k < H; ++k) {
-        const C<T> t = cmul(b[k], w[k]);
         if constexpr (sizeof(T) == 4) {
-          acc_add(Q[j][k].x, Qcx[j][k], t.x);
-          acc_add(Q[j][k].y, Qcy[j][k], t.y);
+          const double bx = b[k].x, by = b[k].y, wx = w[k].x, wy = w[k].y;
+          Q[j][k].x = __builtin_fma(bx, wx, __builtin_fma(-by, wy, Q[j][k].x));
+          Q[j][k].y = __builtin_fma(bx, wy, __builtin_fma(by, wx, Q[j][k].y));
         } else {
+          const C<T> t = cmul(b[k], w[k]);
           Q[j][k].x += t.x;
           Q[j][k].y += t.y;
         }
@@ -169,10 +168,7 @@ __device__ __forceinline__ void gain_x_vss_body(const PipeArgs &a, int bx, int b
     const int e = min(node, a.n_nodes - 1) * a.n_pairs + slot;
     C<T> q[H];
 #pragma unroll
-    for (int k = 0; k < H; ++k) {
-      if constexpr (sizeof(T) == 4) q[k] = C<T>{Q[j][k].x + Qcx[j][k], Q[j][k].y + Qcy[j][k]};
-      else q[k] = Q[j][k];
-    }
+    for (int k = 0; k < H; ++k) q[k] = C<T>{(T)Q[j][k].x, (T)Q[j][k].y};
     fft_pair_dif<N, +1>(q, p);
     C<T> *V = static_cast<C<T> *>(a.V) + (size_t)e * 2 * n3;
     if (live) {
