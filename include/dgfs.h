@@ -10,7 +10,8 @@
  *   - its adjoint (vector-Jacobian product),
  *   - the right-hand side of the non-dimensional Boltzmann equation
  *     (Eq. bzeNonDim) with a nodal discontinuous Galerkin transport term in
- *     one space dimension (Sec. 3.3), and SSP-RK3 / Euler time steps.
+ *     one space dimension (Sec. 3.3) or on a 2-D box of tensor-product
+ *     elements, and SSP-RK3 / Euler time steps.
  *
  * Conventions (every entry point):
  *   - Array arguments are DEVICE pointers owned by the caller unless marked
