@@ -26,7 +26,7 @@ struct DGArgs {
   double Dr[kMaxDG * kMaxDG], Minv[kMaxDG * kMaxDG];
   const double *F;
   double *dF;
-  const double *nw;  // [2][ns] wall densities
+  const double *nw;  // [2][ns][kWallSplit][2] partial wall fluxes (k_wall_density)
 };
 
 __device__ __forceinline__ double grid_c(int j, int N, double L) { return -L + (j + 0.5) * (2.0 * L / N); }
@@ -37,17 +37,22 @@ __device__ __forceinline__ double wall_maxwellian(double m, const double *u, dou
   return a * sqrt(a) * exp(-m * (dx * dx + dy * dy + dz * dz) / T);
 }
 
-// Wall densities n_w from zero discrete net mass flux (one block per wall and
-// species; fixed-order reduction).
-constexpr int kWallThreads = 1024;
+// Wall densities n_w from zero discrete net mass flux: n_w is the outgoing
+// flux of f over the incoming flux of the unit-density wall Maxwellian.  Each
+// (wall, species) is split over kWallSplit blocks, each writing its partial
+// sums (outgoing, unit) in fixed order; the transport kernel adds the partials
+// in block order where it needs n_w, so the result does not depend on timing.
+constexpr int kWallThreads = 1024;  // the 2-D kernel's block
+constexpr int kWall1Threads = 256, kWallSplit = 32;
 
-__global__ void __launch_bounds__(kWallThreads) k_wall_density(DGArgs a, double *nw) {
-  const int wall = blockIdx.x / a.ns, p = blockIdx.x % a.ns;
+__global__ void __launch_bounds__(kWall1Threads) k_wall_density(DGArgs a, double *nw) {
+  const int part = blockIdx.x % kWallSplit, wp = blockIdx.x / kWallSplit;
+  const int wall = wp / a.ns, p = wp % a.ns;
   const int N = a.N, n3 = N * N * N;
   const int node = wall == 0 ? 0 : a.K * (a.P + 1) - 1;
   const double *f = a.F + ((size_t)node * a.ns + p) * n3;
   double out = 0.0, unit = 0.0;
-  for (int v = threadIdx.x; v < n3; v += kWallThreads) {
+  for (int v = part * kWall1Threads + threadIdx.x; v < n3; v += kWall1Threads * kWallSplit) {
     const double cx = grid_c(v / (N * N), N, a.L), cy = grid_c((v / N) % N, N, a.L), cz = grid_c(v % N, N, a.L);
     if (wall == 0) {  // emits c_x > 0, absorbs c_x < 0
       if (cx < 0) out -= cx * f[v];
@@ -57,18 +62,31 @@ __global__ void __launch_bounds__(kWallThreads) k_wall_density(DGArgs a, double 
       else unit -= cx * wall_maxwellian(a.mass[p], a.uw[wall], a.Tw[wall], cx, cy, cz);
     }
   }
-  __shared__ double so[kWallThreads], su[kWallThreads];
+  __shared__ double so[kWall1Threads], su[kWall1Threads];
   so[threadIdx.x] = out;
   su[threadIdx.x] = unit;
   __syncthreads();
-  for (int s = kWallThreads / 2; s > 0; s >>= 1) {
+  for (int s = kWall1Threads / 2; s > 0; s >>= 1) {
     if (threadIdx.x < s) {
       so[threadIdx.x] += so[threadIdx.x + s];
       su[threadIdx.x] += su[threadIdx.x + s];
     }
     __syncthreads();
   }
-  if (threadIdx.x == 0) nw[wall * a.ns + p] = so[0] / su[0];
+  if (threadIdx.x == 0) {
+    nw[2 * (wp * kWallSplit + part)] = so[0];
+    nw[2 * (wp * kWallSplit + part) + 1] = su[0];
+  }
+}
+
+__device__ __forceinline__ double wall_density(const DGArgs &a, int wall, int p) {
+  const double *q = a.nw + 2 * (size_t)((wall * a.ns + p) * kWallSplit);
+  double so = 0.0, su = 0.0;
+  for (int i = 0; i < kWallSplit; ++i) {
+    so += q[2 * i];
+    su += q[2 * i + 1];
+  }
+  return so / su;
 }
 
 // dF/dt = -c_x dF/dx by nodal DG (strong form, upwind flux).  One thread per
@@ -89,13 +107,13 @@ __global__ void __launch_bounds__(256) k_dg_transport(DGArgs a) {
     double uL, uR;
     if (e == 0) {
       const double cy = grid_c((v / N) % N, N, a.L), cz = grid_c(v % N, N, a.L);
-      uL = cx > 0 ? a.nw[p] * wall_maxwellian(a.mass[p], a.uw[0], a.Tw[0], cx, cy, cz) : 0.0;
+      uL = cx > 0 ? wall_density(a, 0, p) * wall_maxwellian(a.mass[p], a.uw[0], a.Tw[0], cx, cy, cz) : 0.0;
     } else {
       uL = f[(size_t)(e * np1 - 1) * ns_stride];
     }
     if (e == a.K - 1) {
       const double cy = grid_c((v / N) % N, N, a.L), cz = grid_c(v % N, N, a.L);
-      uR = cx < 0 ? a.nw[a.ns + p] * wall_maxwellian(a.mass[p], a.uw[1], a.Tw[1], cx, cy, cz) : 0.0;
+      uR = cx < 0 ? wall_density(a, 1, p) * wall_maxwellian(a.mass[p], a.uw[1], a.Tw[1], cx, cy, cz) : 0.0;
     } else {
       uR = f[(size_t)((e + 1) * np1) * ns_stride];
     }
@@ -119,6 +137,7 @@ __global__ void __launch_bounds__(256) k_dg_transport(DGArgs a) {
 // 3 = top; each is periodic or a diffuse wall.
 constexpr int kMax2D = 5;  // P <= 4
 constexpr size_t kWallCap = 8192;  // boundary densities (nodes x species) the workspace holds
+static_assert(2 * DGFS_MAX_SPECIES * kWallSplit * 2 <= kWallCap, "1-D partial wall fluxes exceed the buffer");
 
 struct DG2Args {
   int N, ns, Kx, Ky, P;
@@ -441,7 +460,7 @@ static hipError_t enqueue_rhs(const dgfs_plan_s *pl, const Transport &tr, int64_
     d.F = F;
     d.dF = dF;
     d.nw = nw;
-    DGFS_LAUNCH("k_wall_density", k_wall_density, dim3(2 * ns), dim3(kWallThreads), 0, st, d, nw);
+    DGFS_LAUNCH("k_wall_density", k_wall_density, dim3(2 * ns * kWallSplit), dim3(kWall1Threads), 0, st, d, nw);
     // element slices in y (each thread strides over the rest); species in z
     const unsigned ey = (unsigned)std::min(mesh->K, 64);
     DGFS_LAUNCH("k_dg_transport", k_dg_transport, dim3((unsigned)((n3 + 255) / 256), ey, ns), dim3(256), 0, st, d);
