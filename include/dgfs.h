@@ -336,9 +336,16 @@ int32_t dgfs_profile_read(int32_t cap, char *names, int64_t *counts, double *tot
  * ws_bytes), then at the best width the number of blocks splitting each
  * x-line set's (r, sigma_x) loop in the x-shift stage (1, 2, 4, 8), then
  * whether the x stage of the gain serves a mirrored pair slot in the same
- * pass.  The fastest schedule is kept in the plan; `chosen` (host int32[3],
- * may be NULL) receives (width, split, fusion), split 0 and fusion -1
- * meaning the default was fastest.  The choice is appended to a text cache
+ * pass.  After a warm-up the default schedule is timed first and kept in
+ * each dimension unless a candidate is more than 3% faster; a pick other
+ * than the default is then timed against the default alternately, three
+ * times each, and kept only if its median still wins by that margin (so
+ * that timing noise does not move the schedule).  The pick is kept in the
+ * plan; `chosen` (host int32[3], may be
+ * NULL) receives (width, split, fusion), width 0, split 0 and fusion -1
+ * meaning the default was kept.  Give it at least as many evaluations as a
+ * launch of the widest candidate holds (256 in FP64), or the wide widths
+ * time the same work.  The choice is appended to a text cache
  * (path $DGFS_TUNE_CACHE, default ~/.cache/dgfs_tune.txt) keyed by GPU
  * architecture and plan shape, and dgfs_plan_create reads it unless
  * DGFS_NO_TUNE_CACHE is set.  Synchronises the stream; overwrites Q; must
@@ -348,6 +355,18 @@ int32_t dgfs_profile_read(int32_t cap, char *names, int64_t *counts, double *tot
 dgfs_status dgfs_autotune(dgfs_plan plan, int64_t n_nodes, int32_t p, int32_t q, const double *fp,
                           const double *fq, int64_t node_stride, double *Q, int64_t out_stride,
                           void *ws, size_t ws_bytes, void *stream, int32_t *chosen);
+
+/*
+ * The same search as dgfs_autotune, timing dgfs_rhs (mesh, n_nodes, F, dFdt
+ * and flags as there) instead of one ordered pair: the schedule a
+ * right-hand side or a time step of this shape should run (all its pairs,
+ * the reuse of gain sums, the transport).  ws must hold the right-hand side
+ * of the default schedule; wider candidates that do not fit are skipped.
+ * Overwrites dFdt; otherwise as dgfs_autotune.
+ */
+dgfs_status dgfs_autotune_rhs(dgfs_plan plan, const dgfs_mesh *mesh, int64_t n_nodes, const double *F,
+                              double *dFdt, uint32_t flags, void *ws, size_t ws_bytes, void *stream,
+                              int32_t *chosen);
 
 /* Thread-local message describing the last non-OK status of this thread. */
 const char *dgfs_last_error(void);

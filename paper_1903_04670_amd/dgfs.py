@@ -89,6 +89,8 @@ lib.dgfs_profile_read.restype = _i32
 lib.dgfs_autotune.argtypes = [_vp, _i64, _i32, _i32, _vp, _vp, _i64, _vp, _i64, _vp, _sz, _vp,
                               ct.POINTER(ct.c_int32)]
 lib.dgfs_autotune.restype = ct.c_int
+lib.dgfs_autotune_rhs.argtypes = [_vp, ct.POINTER(Mesh), _i64, _vp, _vp, _u32, _vp, _sz, _vp, ct.POINTER(ct.c_int32)]
+lib.dgfs_autotune_rhs.restype = ct.c_int
 lib.dgfs_last_error.argtypes = []
 lib.dgfs_last_error.restype = ct.c_char_p
 lib.dgfs_sphere_set.argtypes = [_i32, _i32, _dp, _dp]
@@ -99,8 +101,8 @@ lib.dgfs_plan_table.restype = ct.c_int
 EXPORTED = ["dgfs_plan_create", "dgfs_plan_destroy", "dgfs_workspace_bytes", "dgfs_collide",
             "dgfs_collide_vjp", "dgfs_rhs", "dgfs_step", "dgfs_batched_workspace_bytes",
             "dgfs_collide_batched", "dgfs_last_error", "dgfs_sphere_set", "dgfs_plan_table",
-            "dgfs_profile_enable", "dgfs_profile_read", "dgfs_autotune", "dgfs_rhs_2d", "dgfs_step_2d",
-            "dgfs_collide_noalloc"]
+            "dgfs_profile_enable", "dgfs_profile_read", "dgfs_autotune", "dgfs_autotune_rhs", "dgfs_rhs_2d",
+            "dgfs_step_2d", "dgfs_collide_noalloc"]
 
 
 def profile_enable(on=True):
@@ -548,8 +550,9 @@ def collide_batched(plans, items, accumulate=False, ws=None, stream=None):
 def autotune(plan, p, q, fp, fq, out, ws=None, stream=None):
     """Pick the launch schedule for this plan by timing dgfs_collide on the
     given [n_nodes, N, N, N] inputs; returns (chunk width in evaluations
-    per launch, x-shift split or 0 for the default, gain_x fusion 0/1 or -1
-    for the default)."""
+    per launch or 0 for the default, x-shift split or 0 for the default,
+    gain_x fusion 0/1 or -1 for the default).  A dimension leaves its
+    default only for a candidate more than 3% faster."""
     torch = _torch()
     n = fp.shape[0]
     pf, sf = _node_view(fp, plan.N)
@@ -562,4 +565,23 @@ def autotune(plan, p, q, fp, fq, out, ws=None, stream=None):
             ws = torch.empty(max(plan.workspace_bytes(n), 256) * 4, dtype=torch.uint8, device=fp.device)
         _check(lib.dgfs_autotune(plan.handle, n, p, q, pf, pq_, sf, po, so, ct.c_void_p(ws.data_ptr()),
                                  ws.numel(), run.ptr, chosen), "dgfs_autotune")
+    return tuple(int(v) for v in chosen)
+
+
+def autotune_rhs(plan, F, mesh=None, project=False, ws=None, stream=None):
+    """The same search timing dgfs_rhs on F [n_nodes, ns, N, N, N] (with the
+    mesh's transport when given): the schedule for right-hand sides and
+    steps of this shape.  Returns (width, split, fusion) as autotune."""
+    torch = _torch()
+    n = _state(plan, F)
+    chosen = (ct.c_int32 * 3)()
+    out = torch.empty_like(F)
+    with _Launch(stream, F, out, ws) as run:
+        if ws is None:
+            # room for the widest candidate
+            ws = torch.empty(max(plan.workspace_bytes(n, OP_RHS), 256) * 4, dtype=torch.uint8, device=F.device)
+        _check(lib.dgfs_autotune_rhs(plan.handle, ct.byref(mesh) if mesh is not None else None, n,
+                                     ct.c_void_p(F.data_ptr()), ct.c_void_p(out.data_ptr()),
+                                     PROJECT if project else 0, ct.c_void_p(ws.data_ptr()), ws.numel(), run.ptr,
+                                     chosen), "dgfs_autotune_rhs")
     return tuple(int(v) for v in chosen)

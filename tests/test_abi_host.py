@@ -90,6 +90,7 @@ def test_null_arguments():
                                      None) == dgfs.EINVAL
     assert dgfs.lib.dgfs_step(None, None, 1, None, 0.1, 1, 0, None, 0, None) == dgfs.EINVAL
     assert dgfs.lib.dgfs_autotune(None, 1, 0, 0, None, None, 0, None, 0, None, 0, None, None) == dgfs.EINVAL
+    assert dgfs.lib.dgfs_autotune_rhs(None, None, 1, None, None, 0, None, 0, None, None) == dgfs.EINVAL
     # batched: flags other than DGFS_ACCUMULATE, then NULL plans, are refused
     assert dgfs.lib.dgfs_collide_batched(None, 1, None, 0, dgfs.CHECK, None, 0, None) == dgfs.EINVAL
     assert b"flags" in dgfs.lib.dgfs_last_error()

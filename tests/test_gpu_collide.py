@@ -276,10 +276,11 @@ def test_fp32_mixed_radix5_radix7_grids(torch_cuda, N):
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_autotune_schedule(torch_cuda, tmp_path, monkeypatch, precision):
     """The autotuner searches chunk width, x-shift split and the fused
-    k_gain_x pass, stores its pick in the cache, and every schedule (the
-    tuned one, each split, each fusion setting, a cached one) gives
-    bit-identical results, for a single cross pair and for the symmetric
-    two-species right-hand side (mirrored slots, half-set self pairs)."""
+    k_gain_x pass (0 / -1: the default kept), stores its pick in the cache,
+    and every schedule (the tuned one, each split, each fusion setting, a
+    cached one) gives bit-identical results, for a single cross pair and for
+    the symmetric two-species right-hand side (mirrored slots, half-set self
+    pairs)."""
     from paper_1903_04670_amd import dgfs
     torch = torch_cuda
     monkeypatch.setenv("DGFS_TUNE_CACHE", str(tmp_path / "tune.txt"))
@@ -290,7 +291,7 @@ def test_autotune_schedule(torch_cuda, tmp_path, monkeypatch, precision):
     ref_rhs = dgfs.rhs(pl, F)
     out = torch.empty_like(ref)
     width, split, fuse = dgfs.autotune(pl, 0, 1, F[:, 0], F[:, 1], out)
-    assert width in (8, 16, 32, 64, 128, 256)
+    assert width in (0, 8, 16, 32, 64, 128, 256)
     assert split in (0, 1, 2, 4, 8) and fuse in (-1, 0, 1)
     assert (tmp_path / "tune.txt").read_text().strip().endswith("|%d,%d,%d" % (width, split, fuse))
     torch.cuda.synchronize()

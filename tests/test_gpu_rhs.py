@@ -74,6 +74,30 @@ def test_couette_rhs_matches_oracle(torch_cuda):
     assert err <= TOL
 
 
+def test_autotune_rhs_keeps_results(torch_cuda, tmp_path, monkeypatch):
+    """dgfs_autotune_rhs times the right-hand side (all pairs, transport)
+    over the autotuner's schedule dimensions and stores its pick; the
+    right-hand side and a graph-replayed step then give the same bits as
+    under the default schedule."""
+    from paper_1903_04670_amd import dgfs
+    torch = torch_cuda
+    monkeypatch.setenv("DGFS_TUNE_CACHE", str(tmp_path / "tune.txt"))
+    cfg = _couette_small()
+    pl = gpu_plan(cfg, dg_order=cfg["P"])
+    mesh = dgfs.make_mesh(cfg["K"])
+    F = torch.from_numpy(cfg["F"]).cuda()
+    ref = dgfs.rhs(pl, F, mesh=mesh)
+    G = F.clone()
+    dgfs.step(pl, G, 1e-3, 2, mesh=mesh)
+    width, split, fuse = dgfs.autotune_rhs(pl, F, mesh=mesh)
+    assert width in (0, 8, 16, 32, 64) and split in (0, 1, 2, 4, 8) and fuse in (-1, 0, 1)
+    assert (tmp_path / "tune.txt").read_text().strip().endswith("|%d,%d,%d" % (width, split, fuse))
+    assert torch.equal(dgfs.rhs(pl, F, mesh=mesh), ref)
+    H = F.clone()
+    dgfs.step(pl, H, 1e-3, 2, mesh=mesh)
+    assert torch.equal(H, G)
+
+
 @pytest.mark.parametrize("K,P", [(70, 1), (129, 2)])
 def test_couette_rhs_more_elements_than_grid_slices(torch_cuda, K, P):
     """The transport kernel spreads the elements over at most 64 slices and
