@@ -36,7 +36,8 @@
  *         buffer (hipHostMalloc when a larger one is needed), waits on the
  *         host for the previous call's copy from that buffer, and serialises
  *         concurrent callers on a process-wide lock;
- *       * dgfs_autotune synchronises the stream and creates timing events;
+ *       * dgfs_autotune and dgfs_autotune_rhs synchronise the stream and
+ *         create timing events;
  *       * while dgfs_profile_enable is on, every launch creates two events.
  *   - `ws` / `ws_bytes`: caller-owned device workspace of at least
  *     dgfs_workspace_bytes(plan, n_nodes, op) bytes, 256-byte aligned.
@@ -44,9 +45,10 @@
  *     launch error is returned as DGFS_EHIP.  Nothing throws across the ABI;
  *     dgfs_last_error() gives a thread-local message for the last non-OK
  *     status.
- *   - A plan is immutable after creation, except that dgfs_autotune stores
- *     the chunk width it picks in it, and may be used concurrently on
- *     different streams with distinct workspaces (dgfs_autotune excepted).
+ *   - A plan is immutable after creation, except that dgfs_autotune and
+ *     dgfs_autotune_rhs store the schedule they pick in it, and may be used
+ *     concurrently on different streams with distinct workspaces (the two
+ *     autotuners excepted).
  */
 #ifndef DGFS_H
 #define DGFS_H
