@@ -78,6 +78,22 @@ def test_vss_radix5_grid_N40(torch_cuda):
         assert rel_linf(got[0], ref) <= TOL, (p, q)
 
 
+def test_vss_radix7_grid_N56(torch_cuda):
+    """A VSS plan (alpha = 1.3) on N = 56 = 8 x 7, where the gain kernels run
+    one group of 2N lanes per block: one node, a cross pair and a self pair,
+    octahedron, N_rho = 2, against the oracle at 1e-11."""
+    from paper_1903_04670_amd import dgfs
+    torch = torch_cuda
+    cfg = vss_config(56, ns=2, kind="octahedron", Nrho=2, seed=56, n_nodes=1, alpha=1.3)
+    pl = gpu_plan(cfg)
+    opl = oracle_pairs(cfg)
+    F = torch.from_numpy(cfg["F"]).cuda()
+    for p, q in [(0, 1), (1, 1)]:
+        got = dgfs.collide(pl, p, q, F[:, p], F[:, q]).cpu().numpy()
+        ref = oracle_collide(opl[p][q], cfg["F"][0, p], cfg["F"][0, q])
+        assert rel_linf(got[0], ref) <= TOL, (p, q)
+
+
 def _vss_cfg5_shape(n_nodes=1, Nrho=2):
     """The precision workload's collision shape (three species, masses 1, 2,
     4, alpha = 1.4, N = 48, Fibonacci M = 32) with N_rho = 2: the kernels'
