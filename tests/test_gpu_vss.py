@@ -147,6 +147,28 @@ def test_vss_cfg5_shape_N48_fp32_mixed_against_oracle(torch_cuda):
         assert err_l <= 2e-6 and err_q <= 5e-4
 
 
+@pytest.mark.parametrize("N", [40, 56])
+def test_vss_fp32_mixed_radix5_radix7_grids(torch_cuda, N):
+    """FP32-mixed VSS plans (alpha = 1.3, octahedron, N_rho = 2) on N = 40
+    and 56, a cross pair and a self pair against the FP64 oracle within the
+    FP32 bounds: 2e-6 of the loss term, 5e-4 of Q."""
+    from oracle.collide import collide_gain_loss
+    from paper_1903_04670_amd import dgfs
+    torch = torch_cuda
+    cfg = vss_config(N, ns=2, kind="octahedron", Nrho=2, seed=N + 1, n_nodes=1, alpha=1.3)
+    pl = gpu_plan(cfg, precision="fp32")
+    opl = oracle_pairs(cfg)
+    F = torch.from_numpy(cfg["F"]).cuda()
+    for p, q in [(0, 1), (1, 1)]:
+        got = dgfs.collide(pl, p, q, F[:, p], F[:, q]).cpu().numpy()[0]
+        gain, loss = collide_gain_loss(opl[p][q], cfg["F"][0, p], cfg["F"][0, q])
+        ref = gain - loss
+        err_q = rel_linf(got, ref)
+        err_l = float(np.max(np.abs(got - ref)) / np.max(np.abs(loss)))
+        print("VSS N=%d fp32-mixed (%d,%d): rel to |Q| %.3e, rel to |loss| %.3e" % (N, p, q, err_q, err_l))
+        assert err_l <= 2e-6 and err_q <= 5e-4
+
+
 def test_vss_three_species_rhs_N16(torch_cuda):
     """Three species (masses 1, 2, 4), alpha = 1.4, Fibonacci M = 32,
     N_rho = 8 at N = 16: the mixture collision term against the oracle."""
