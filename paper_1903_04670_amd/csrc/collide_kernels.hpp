@@ -272,8 +272,14 @@ __device__ __forceinline__ void fwd_yz_body(const FwdArgs &a, int bx, int tid, C
   const size_t n3 = (size_t)N * N * N;
   if (active) {
     const double *f = a.src[slot] + (size_t)node * a.node_stride + (size_t)jx * N * N;
-    // stage the real plane: element (y, z) -> lds[y][z]
-    for (int i = t; i < N * N; i += N) lds[g][i / N][i % N] = C<T>{(T)f[i], (T)0};
+    // stage the real plane: element (y, z) -> lds[y][z]; thread t moves
+    // column z = t, its N loads issued together (a runtime loop here waited
+    // for each load before issuing the next)
+    double v[N];
+#pragma unroll
+    for (int y = 0; y < N; ++y) v[y] = f[y * N + t];
+#pragma unroll
+    for (int y = 0; y < N; ++y) lds[g][y][t] = C<T>{(T)v[y], (T)0};
   }
   __syncthreads();
   if (active) {

@@ -297,17 +297,41 @@ __global__ void __launch_bounds__(kProjThreads) k_proj_moments(ProjArgs a) {
   for (int i = 0; i < k; ++i) mom[i] = 0.0;
   const int per = (total + a.nblk - 1) / a.nblk;
   const int lo = blk * per, hi = min(total, lo + per);
-  for (int i = lo + threadIdx.x; i < hi; i += kProjThreads) {
-    const int sp = i / n3, v = i % n3;
-    const double q = Q[(size_t)sp * n3 + v], m = a.mass[sp];
-    const double cx = grid_c(v / (N * N), N, a.L), cy = grid_c((v / N) % N, N, a.L), cz = grid_c(v % N, N, a.L);
-    mom[sp] += w * q;
-    if (k > a.nsp) {
-      mom[a.nsp + 0] += w * m * cx * q;
-      mom[a.nsp + 1] += w * m * cy * q;
-      mom[a.nsp + 2] += w * m * cz * q;
-      mom[a.nsp + 3] += w * 0.5 * m * (cx * cx + cy * cy + cz * cz) * q;
+  // species of the block's range in turn (a uniform loop, so the mass is a
+  // scalar read), points unrolled so that several loads are in flight
+  double px = 0.0, py = 0.0, pz = 0.0, en = 0.0;
+  for (int sp = lo / n3; sp < a.nsp && sp * n3 < hi; ++sp) {
+    const int s0 = max(lo, sp * n3), s1 = min(hi, (sp + 1) * n3);
+    const double m = a.mass[sp];
+    const double *Qs = Q + (size_t)sp * n3;
+    double ms = 0.0;
+#pragma unroll 4
+    for (int i = s0 + threadIdx.x; i < s1; i += kProjThreads) {
+      const int v = i - sp * n3;
+      const double q = Qs[v];
+      const double cx = grid_c(v / (N * N), N, a.L), cy = grid_c((v / N) % N, N, a.L), cz = grid_c(v % N, N, a.L);
+      ms += w * q;
+      if (k > a.nsp) {
+        px += w * m * cx * q;
+        py += w * m * cy * q;
+        pz += w * m * cz * q;
+        en += w * 0.5 * m * (cx * cx + cy * cy + cz * cz) * q;
+      }
     }
+#pragma unroll
+    for (int s = 0; s < DGFS_MAX_SPECIES; ++s)
+      if (s == sp) mom[s] += ms;
+  }
+  if (k > a.nsp) {
+    // static indices keep mom in registers; nsp may equal the maximum
+#pragma unroll
+    for (int s = 0; s <= DGFS_MAX_SPECIES; ++s)
+      if (s == a.nsp) {
+        mom[s] += px;
+        mom[s + 1] += py;
+        mom[s + 2] += pz;
+        mom[s + 3] += en;
+      }
   }
   __shared__ double red[DGFS_MAX_SPECIES + 4][kProjThreads];
   for (int i = 0; i < k; ++i) red[i][threadIdx.x] = mom[i];
@@ -342,18 +366,38 @@ __global__ void __launch_bounds__(kProjThreads) k_proj_apply(ProjArgs a) {
   const double *Q = a.Q + (size_t)node * a.q_stride;
   const int per = (total + a.nblk - 1) / a.nblk;
   const int lo = blk * per, hi = min(total, lo + per);
-  for (int i = lo + threadIdx.x; i < hi; i += kProjThreads) {
-    const int sp = i / n3, v = i % n3;
-    const double m = a.mass[sp];
-    const double cx = grid_c(v / (N * N), N, a.L), cy = grid_c((v / N) % N, N, a.L), cz = grid_c(v % N, N, a.L);
-    const double corr =
-        k > a.nsp ? w * (lam[sp] + m * (lam[a.nsp] * cx + lam[a.nsp + 1] * cy + lam[a.nsp + 2] * cz) +
-                         0.5 * m * (cx * cx + cy * cy + cz * cz) * lam[a.nsp + 3])
-                  : w * lam[sp];
-    const double val = Q[(size_t)sp * n3 + v] - corr;
+  // species of the block's range in turn (uniform: mass, output pointer and
+  // multipliers are scalar reads), points unrolled
+  for (int sp = lo / n3; sp < a.nsp && sp * n3 < hi; ++sp) {
+    const int s0 = max(lo, sp * n3), s1 = min(hi, (sp + 1) * n3);
+    const double m = a.mass[sp], l0 = lam[sp];
+    const double lx = k > a.nsp ? lam[a.nsp] : 0.0, ly = k > a.nsp ? lam[a.nsp + 1] : 0.0;
+    const double lz = k > a.nsp ? lam[a.nsp + 2] : 0.0, le = k > a.nsp ? lam[a.nsp + 3] : 0.0;
+    const double *Qs = Q + (size_t)sp * n3;
     double *o = a.out[sp] + (size_t)node * a.out_stride;
-    if (a.accumulate) o[v] += val;
-    else o[v] = val;
+    // chunks of kU points per thread: all loads of a chunk are issued
+    // before its first store (a store may alias the next load otherwise)
+    constexpr int kU = 4;
+    for (int i0 = s0 - sp * n3 + threadIdx.x; i0 < s1 - sp * n3; i0 += kU * kProjThreads) {
+      double q[kU], prev[kU];
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        const int v = i0 + u * kProjThreads;
+        const bool in = v < s1 - sp * n3;
+        q[u] = in ? Qs[v] : 0.0;
+        prev[u] = in && a.accumulate ? o[v] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        const int v = i0 + u * kProjThreads;
+        if (v >= s1 - sp * n3) break;
+        const double cx = grid_c(v / (N * N), N, a.L), cy = grid_c((v / N) % N, N, a.L), cz = grid_c(v % N, N, a.L);
+        const double corr =
+            k > a.nsp ? w * (l0 + m * (lx * cx + ly * cy + lz * cz) + 0.5 * m * (cx * cx + cy * cy + cz * cz) * le)
+                      : w * l0;
+        o[v] = prev[u] + (q[u] - corr);
+      }
+    }
   }
 }
 
