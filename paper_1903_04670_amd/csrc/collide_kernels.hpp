@@ -1174,11 +1174,17 @@ __device__ __forceinline__ void final_yz_body(const PipeArgs &a, const FinalArgs
   }
   if (active) {
     double *out = fa.out[o] + (size_t)node * fa.out_stride + (size_t)jx * N * N;
+    // the branch is uniform; taken outside the loop, the H reads of the
+    // accumulated output are issued together instead of one per store
+    if (fa.accumulate) {
+      double prev[H];
 #pragma unroll
-    for (int k = 0; k < H; ++k) {
-      const int idx = (p * H + k) * N + c;
-      if (fa.accumulate) out[idx] += acc[k];
-      else out[idx] = acc[k];
+      for (int k = 0; k < H; ++k) prev[k] = out[(p * H + k) * N + c];
+#pragma unroll
+      for (int k = 0; k < H; ++k) out[(p * H + k) * N + c] = prev[k] + acc[k];
+    } else {
+#pragma unroll
+      for (int k = 0; k < H; ++k) out[(p * H + k) * N + c] = acc[k];
     }
   }
 }
