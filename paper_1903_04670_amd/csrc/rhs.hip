@@ -91,8 +91,13 @@ __device__ __forceinline__ double wall_density(const DGArgs &a, int wall, int p)
 
 // dF/dt = -c_x dF/dx by nodal DG (strong form, upwind flux).  One thread per
 // (species, velocity point, element); blockIdx.y strides over the elements.
+// The degree is a template argument so that the element's P + 1 loads, its
+// two neighbour loads and its stores are issued together (with a run-time
+// degree each load was waited for before the next).
+template <int P>
 __global__ void __launch_bounds__(256) k_dg_transport(DGArgs a) {
-  const int N = a.N, n3 = N * N * N, P = a.P, np1 = a.P + 1;
+  constexpr int np1 = P + 1;
+  const int N = a.N, n3 = N * N * N;
   const int v = blockIdx.x * blockDim.x + threadIdx.x;
   const int p = blockIdx.z;
   if (v >= n3) return;
@@ -102,30 +107,37 @@ __global__ void __launch_bounds__(256) k_dg_transport(DGArgs a) {
   double *df = a.dF + (size_t)p * n3 + v;
   const double s = 2.0 / a.h;
   for (int e = blockIdx.y; e < a.K; e += gridDim.y) {
-    double u[kMaxDG];
-    for (int i = 0; i <= P; ++i) u[i] = f[(size_t)(e * np1 + i) * ns_stride];
-    double uL, uR;
+    // neighbour nodes across the two faces; at a wall the index is any valid
+    // one and its value is replaced by the wall's inflow below
+    const int iL = e > 0 ? e * np1 - 1 : 0, iR = e < a.K - 1 ? (e + 1) * np1 : 0;
+    double u[np1];
+#pragma unroll
+    for (int i = 0; i < np1; ++i) u[i] = f[(size_t)(e * np1 + i) * ns_stride];
+    double uL = f[(size_t)iL * ns_stride], uR = f[(size_t)iR * ns_stride];
     if (e == 0) {
       const double cy = grid_c((v / N) % N, N, a.L), cz = grid_c(v % N, N, a.L);
       uL = cx > 0 ? wall_density(a, 0, p) * wall_maxwellian(a.mass[p], a.uw[0], a.Tw[0], cx, cy, cz) : 0.0;
-    } else {
-      uL = f[(size_t)(e * np1 - 1) * ns_stride];
     }
     if (e == a.K - 1) {
       const double cy = grid_c((v / N) % N, N, a.L), cz = grid_c(v % N, N, a.L);
       uR = cx < 0 ? wall_density(a, 1, p) * wall_maxwellian(a.mass[p], a.uw[1], a.Tw[1], cx, cy, cz) : 0.0;
-    } else {
-      uR = f[(size_t)((e + 1) * np1) * ns_stride];
     }
     // boundary terms n (c u - F*) with the upwind flux F*
     const double termR = cx > 0 ? 0.0 : cx * (u[P] - uR);
     const double termL = cx > 0 ? -cx * (u[0] - uL) : 0.0;
-    for (int i = 0; i <= P; ++i) {
+#pragma unroll
+    for (int i = 0; i < np1; ++i) {
       double d = 0.0;
-      for (int j = 0; j <= P; ++j) d += a.Dr[i * np1 + j] * u[j];
+#pragma unroll
+      for (int j = 0; j < np1; ++j) d += a.Dr[i * np1 + j] * u[j];
       df[(size_t)(e * np1 + i) * ns_stride] = s * (-cx * d + a.Minv[i * np1 + P] * termR + a.Minv[i * np1] * termL);
     }
   }
+}
+
+template <int P>
+static void launch_dg_transport(dim3 grid, hipStream_t st, const DGArgs &d) {
+  DGFS_LAUNCH("k_dg_transport", k_dg_transport<P>, grid, dim3(256), 0, st, d);
 }
 
 // ------------------------------------------------------------ 2-D transport
@@ -507,7 +519,17 @@ static hipError_t enqueue_rhs(const dgfs_plan_s *pl, const Transport &tr, int64_
     DGFS_LAUNCH("k_wall_density", k_wall_density, dim3(2 * ns * kWallSplit), dim3(kWall1Threads), 0, st, d, nw);
     // element slices in y (each thread strides over the rest); species in z
     const unsigned ey = (unsigned)std::min(mesh->K, 64);
-    DGFS_LAUNCH("k_dg_transport", k_dg_transport, dim3((unsigned)((n3 + 255) / 256), ey, ns), dim3(256), 0, st, d);
+    const dim3 grid((unsigned)((n3 + 255) / 256), ey, ns);
+    switch (pl->P) {  // a mesh needs 1 <= P; the plan admits P <= 8
+      case 1: launch_dg_transport<1>(grid, st, d); break;
+      case 2: launch_dg_transport<2>(grid, st, d); break;
+      case 3: launch_dg_transport<3>(grid, st, d); break;
+      case 4: launch_dg_transport<4>(grid, st, d); break;
+      case 5: launch_dg_transport<5>(grid, st, d); break;
+      case 6: launch_dg_transport<6>(grid, st, d); break;
+      case 7: launch_dg_transport<7>(grid, st, d); break;
+      default: launch_dg_transport<8>(grid, st, d); break;
+    }
   }
   if (tr.m2) {
     const dgfs_mesh2d *m = tr.m2;

@@ -118,6 +118,23 @@ def test_couette_rhs_more_elements_than_grid_slices(torch_cuda, K, P):
     assert err <= TOL
 
 
+@pytest.mark.parametrize("P", [4, 5, 6, 7, 8])
+def test_couette_rhs_higher_degrees(torch_cuda, P):
+    """DG degrees 4 ... 8 (the transport kernel is compiled per degree; the
+    other tests cover 1 ... 3): the right-hand side against the oracle on
+    three elements between diffuse walls."""
+    from paper_1903_04670_amd import dgfs
+    torch = torch_cuda
+    cfg = _couette_small(N=6, K=3, P=P, seed=30 + P)
+    prob, coll = _oracle_rhs(cfg, cfg["F"])
+    pl = gpu_plan(cfg, dg_order=P)
+    mesh = dgfs.make_mesh(cfg["K"])
+    got = dgfs.rhs(pl, torch.from_numpy(cfg["F"]).cuda(), mesh=mesh).cpu().numpy()
+    err = rel_linf(got, prob.rhs(cfg["F"], coll))
+    print("P=%d rhs: rel Linf %.3e" % (P, err))
+    assert err <= TOL
+
+
 @pytest.mark.parametrize("sphere", ["icosahedron", "octahedron"])
 def test_symmetric_gain_schedule_three_species(torch_cuda, sphere, monkeypatch):
     """Mixture collision term of three species: the (q, p) gain sums reused
@@ -180,6 +197,30 @@ def test_projected_rhs_conserves(torch_cuda):
         mom = cons.moments(got[i], cfg["N"], cfg["L"], cfg["masses"])
         scale = cons.moments(np.abs(C[i]), cfg["N"], cfg["L"], cfg["masses"])
         assert np.max(np.abs(mom) / np.max(np.abs(scale))) < 1e-12
+
+
+def test_projection_with_the_most_species(torch_cuda):
+    """Four species, the most a plan takes (the moment rows are the four
+    masses, then momentum and energy): the projected collision term against
+    the oracle's projection with vanishing moments, and the same term added
+    onto the transport term of a Couette mesh."""
+    from paper_1903_04670_amd import dgfs
+    torch = torch_cuda
+    cfg = _couette_small(N=8, K=2, P=1, seed=21, ns=4)
+    prob, coll = _oracle_rhs(cfg, cfg["F"], project=True)
+    C = mixture_collision(oracle_pairs(cfg), cfg["F"])
+    ref = coll(cfg["F"])
+    pl = gpu_plan(cfg, dg_order=cfg["P"])
+    F = torch.from_numpy(cfg["F"]).cuda()
+    got = dgfs.rhs(pl, F, project=True).cpu().numpy()
+    assert rel_linf(got, ref) <= TOL
+    for i in range(cfg["n_nodes"]):
+        mom = cons.moments(got[i], cfg["N"], cfg["L"], cfg["masses"])
+        scale = cons.moments(np.abs(C[i]), cfg["N"], cfg["L"], cfg["masses"])
+        assert np.max(np.abs(mom) / np.max(np.abs(scale))) < 1e-12, i
+    mesh = dgfs.make_mesh(cfg["K"])
+    got = dgfs.rhs(pl, F, mesh=mesh, project=True).cpu().numpy()
+    assert rel_linf(got, prob.rhs(cfg["F"], coll)) <= TOL
 
 
 def test_euler_steps_with_mesh_and_projection(torch_cuda):
