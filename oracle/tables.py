@@ -121,16 +121,16 @@ def legendre_all(nmax, t):
 
 def funk_hecke_coeffs(eta, nmax):
     """a_n = (2n+1)/2 int_{-1}^{1} (1+t)^eta P_n(t) dt, n = 0..nmax, from
-    int (1+t)^eta P_n = 2^{eta+1} eta(eta-1)..(eta-n+1) / ((eta+1)..(eta+n+1))."""
+    int (1+t)^eta P_n = 2^{eta+1} eta(eta-1)..(eta-n+1) / ((eta+1)..(eta+n+1)).
+    The ratio of the two products is carried as one number, r_0 = 1/(eta+1),
+    r_n = r_{n-1} (eta-n+1)/(eta+n+1): each product alone overflows past
+    n = 170, which the series reaches at the largest |k| of an N = 48 grid."""
     a = np.zeros(nmax + 1)
+    r = 1.0 / (eta + 1.0)
     for n in range(nmax + 1):
-        num = 1.0
-        for j in range(n):
-            num *= eta - j
-        den = 1.0
-        for j in range(1, n + 2):
-            den *= eta + j
-        a[n] = 0.5 * (2 * n + 1) * 2.0 ** (eta + 1.0) * num / den
+        if n > 0:
+            r *= (eta - n + 1) / (eta + n + 1)
+        a[n] = 0.5 * (2 * n + 1) * 2.0 ** (eta + 1.0) * r
     return a
 
 

@@ -110,6 +110,24 @@ def test_funk_hecke_coefficients_by_quadrature(eta):
         assert a[0] == 1.0 and np.all(a[1:] == 0.0)
 
 
+@pytest.mark.parametrize("eta", [0.4, -0.3, 2.0])
+def test_funk_hecke_coefficients_high_orders(eta):
+    """Orders up to 240 (the series at the largest |k| of an N = 48 grid needs
+    about 180): against a Gauss-Jacobi rule with weight (1+t)^eta, exact for
+    the polynomial P_n.  For integer eta the coefficients vanish past n = eta.
+    The rule's own sum over ~120 nodes carries about 1e-12 of rounding, hence
+    the 1e-10 bar; an overflow or a wrong factor misses by order one."""
+    nmax = 240
+    a = tb.funk_hecke_coeffs(eta, nmax)
+    assert np.all(np.isfinite(a))
+    t, w = sp.roots_jacobi(nmax // 2 + 2, 0.0, eta)
+    for n in range(nmax + 1):
+        ref = 0.5 * (2 * n + 1) * np.sum(w * sp.eval_legendre(n, t))
+        assert abs(a[n] - ref) <= 1e-10 * max(1.0, abs(ref)), (n, a[n], ref)
+    if eta == 2.0:
+        assert np.all(a[3:] == 0.0)
+
+
 def _phi_bruteforce(x, khat, sig, eta, nt=400, nphi=400):
     """int_{S^2} (1 + sig.u)^eta exp(-i x khat.u) du by a product rule:
     Gauss-Legendre in cos(theta) about sig, trapezoid in azimuth."""
@@ -131,7 +149,8 @@ def _phi_bruteforce(x, khat, sig, eta, nt=400, nphi=400):
 @pytest.mark.parametrize("eta", [0.0, 0.4])
 def test_sphere_integral_closed_forms(eta):
     rng = np.random.default_rng(7)
-    for x in (0.0, 0.7, 3.1, 9.5):
+    # x up to 94: the largest argument of the N = 48, N_rho = 24 gain table
+    for x in (0.0, 0.7, 3.1, 9.5, 60.0, 94.0):
         k = rng.standard_normal(3)
         k /= np.linalg.norm(k)
         s = rng.standard_normal(3)
