@@ -182,6 +182,59 @@ def test_vss_three_species_rhs_N16(torch_cuda):
     assert rel_linf(got, ref) <= TOL
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_vss_cfg5_full_shape_all_pairs_against_stored_oracle(torch_cuda, precision):
+    """The precision workload at its full shape (three species, N = 48,
+    Fibonacci M = 32, N_rho = 24, alpha = 1.4): all nine ordered pairs at two
+    nodes against the oracle's terms, stored by
+    tests/golden/make_vss_cfg5_oracle.py as 96 sampled points, 32 points
+    where |Q| >= 1% of max |Q|, the point of max |Q| and four projections of
+    the whole term onto seeded normal weights.  FP64: every compared point within 1e-11 of max |Q|, and each
+    projection within 1e-11 max |Q| ||W||_2 (the size an error of that bar,
+    independent of the weights, takes in the projection).  FP32-mixed: the
+    bounds stated for that path, 2e-6 of max |loss| and 5e-4 of max |Q|,
+    and the projections within 2e-6 max |loss| ||W||_2."""
+    import json
+    import os
+    from paper_1903_04670_amd import dgfs, workloads as wl
+    torch = torch_cuda
+    with open(os.path.join(os.path.dirname(__file__), "golden", "vss_cfg5_oracle.json")) as fh:
+        gold = json.load(fh)
+    nodes = gold["nodes"]
+    cfg = wl.precision_vss(n_nodes=nodes)
+    F = cfg["F"]
+    # the seeded input must be the one the stored terms were computed from
+    assert list(F.shape) == gold["inputs"]["shape"]
+    for i in range(nodes):
+        for p in range(cfg["ns"]):
+            s = gold["inputs"]["sums"][i][p]
+            assert abs(F[i, p].sum() - s) <= 1e-12 * abs(s)
+            assert abs(F[i, p].flat[0] - gold["inputs"]["first"][i][p]) <= 1e-15 * abs(F[i, p].flat[0])
+    n3 = cfg["N"] ** 3
+    idx = np.asarray(gold["sample_idx"])
+    W = np.random.default_rng(gold["proj_seed"]).standard_normal((gold["n_proj"], n3))
+    wn = np.linalg.norm(W, axis=1)
+    pl = gpu_plan(cfg, precision=precision)
+    Fd = torch.from_numpy(F).cuda()
+    assert len(gold["pairs"]) == cfg["ns"] ** 2
+    for key, ref_nodes in gold["pairs"].items():
+        p, q = map(int, key.split(","))
+        got = dgfs.collide(pl, p, q, Fd[:, p], Fd[:, q]).cpu().numpy().reshape(nodes, n3)
+        for i, g in enumerate(ref_nodes):
+            Q = got[i]
+            e_pt = max(float(np.max(np.abs(Q[idx] - np.asarray(g["samples"])))),
+                       float(np.max(np.abs(Q[np.asarray(g["bulk_idx"])] - np.asarray(g["bulk"])))),
+                       abs(Q[g["argmax"]] - g["at_argmax"]))
+            e_proj = np.abs(W @ Q - np.asarray(g["proj"])) / wn
+            print("%s pair (%d,%d) node %d: points %.3e, projections %.3e of max|Q|; %.3e of max|loss|"
+                  % (precision, p, q, i, e_pt / g["qmax"], e_proj.max() / g["qmax"], e_pt / g["lossmax"]))
+            if precision == "fp64":
+                assert e_pt <= TOL * g["qmax"] and np.all(e_proj <= TOL * g["qmax"]), (p, q, i)
+            else:
+                assert e_pt <= 2e-6 * g["lossmax"] and e_pt <= 5e-4 * g["qmax"], (p, q, i)
+                assert np.all(e_proj <= 2e-6 * g["lossmax"]), (p, q, i)
+
+
 def test_vss_N48_fp32_mixed_vs_fp64_and_projection(torch_cuda):
     """The precision workload at full velocity size (N = 48, M = 32 Fibonacci,
     N_rho = 24, three species, alpha = 1.4) on 2 nodes: FP32-mixed with the

@@ -245,6 +245,43 @@ def test_gain_minus_loss_equals_collide():
         gain, loss = collide_gain_loss(pl, f, g)
         Q = collide(pl, f, g)
         assert np.max(np.abs(gain - loss - Q)) <= 1e-14 * np.max(np.abs(loss))
+    # a VSS plan (direction-dependent gain table)
+    s, w = sphere_set("fibonacci", 7)
+    pl = PairPlan(8, 5.0, 1.0, 2.0, 0.6, 1.4, 3, s, w, R=4.0)
+    f, g = rng.random((8, 8, 8)), rng.random((8, 8, 8))
+    gain, loss = collide_gain_loss(pl, f, g)
+    assert np.max(np.abs(gain - loss - collide(pl, f, g))) <= 1e-14 * np.max(np.abs(loss))
+
+
+def test_stored_full_shape_vss_terms_match_this_input():
+    """The oracle terms stored for the full-shape VSS precision workload
+    (tests/golden/make_vss_cfg5_oracle.py) were computed from the input the
+    seeded workload generator gives here, and are self-consistent: nine
+    ordered pairs at two nodes, finite, |Q| at the stored argmax equal to the
+    stored max, bulk points at >= 1% of it, projections within their scales."""
+    import json
+    with open(os.path.join(GOLDEN, "vss_cfg5_oracle.json")) as fh:
+        gold = json.load(fh)
+    cfg = wl.precision_vss(n_nodes=gold["nodes"])
+    F = cfg["F"]
+    assert list(F.shape) == gold["inputs"]["shape"]
+    for i in range(gold["nodes"]):
+        for p in range(cfg["ns"]):
+            assert abs(F[i, p].sum() - gold["inputs"]["sums"][i][p]) <= 1e-12 * abs(gold["inputs"]["sums"][i][p])
+            assert abs(F[i, p].flat[0] - gold["inputs"]["first"][i][p]) <= 1e-15 * abs(F[i, p].flat[0])
+    assert sorted(gold["pairs"]) == ["%d,%d" % (p, q) for p in range(3) for q in range(3)]
+    n3 = cfg["N"] ** 3
+    assert len(gold["sample_idx"]) == gold["n_samples"] and max(gold["sample_idx"]) < n3
+    for nodes in gold["pairs"].values():
+        assert len(nodes) == gold["nodes"]
+        for g in nodes:
+            vals = np.asarray(g["samples"] + g["bulk"] + [g["at_argmax"], g["qmax"], g["lossmax"]] + g["proj"])
+            assert np.all(np.isfinite(vals))
+            assert abs(g["at_argmax"]) == g["qmax"] > 0 and g["lossmax"] > 0
+            assert np.all(np.abs(g["samples"]) <= g["qmax"])
+            assert len(g["bulk"]) == 32 and max(g["bulk_idx"]) < n3
+            assert np.all(np.abs(g["bulk"]) >= 0.01 * g["qmax"]) and np.all(np.abs(g["bulk"]) <= g["qmax"])
+            assert np.all(np.abs(g["proj"]) <= np.asarray(g["proj_scale"]))
 
 
 @pytest.mark.parametrize("sphere,nyq", [("octahedron", False), ("icosahedron", False),
