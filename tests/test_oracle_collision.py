@@ -284,6 +284,33 @@ def test_stored_full_shape_vss_terms_match_this_input():
             assert np.all(np.abs(g["proj"]) <= np.asarray(g["proj_scale"]))
 
 
+def test_stored_couette_step_matches_this_input():
+    """The oracle's full Couette SSP-RK3 step stored by
+    tests/golden/make_couette_step_oracle.py was computed from the input the
+    seeded workload generator gives here, and is self-consistent: finite,
+    each stored peak equal to its array's max and at most the global max,
+    bulk points at >= 1% of their peak."""
+    import json
+    with open(os.path.join(GOLDEN, "couette_step_oracle.json")) as fh:
+        gold = json.load(fh)
+    cfg = wl.couette_two_species()
+    F = cfg["F"]
+    assert list(F.shape) == gold["inputs"]["shape"] and gold["dt"] == cfg["dt"]
+    assert abs(F.sum() - gold["inputs"]["total"]) <= 1e-12 * abs(gold["inputs"]["total"])
+    n3 = cfg["N"] ** 3
+    assert max(gold["sample_idx"]) < n3 and len(gold["proj"]) == gold["n_proj"]
+    for k, nd in enumerate(gold["nodes"]):
+        assert 0 <= nd["node"] < cfg["n_nodes"]
+        for p, g in enumerate(nd["species"]):
+            ref = gold["inputs"]["sums"][k][p]
+            assert abs(F[nd["node"], p].sum() - ref) <= 1e-12 * abs(ref)
+            vals = np.asarray(g["samples"] + g["bulk"] + [g["at_argmax"]])
+            assert np.all(np.isfinite(vals))
+            assert abs(g["at_argmax"]) == g["amax"] <= gold["dmax"]
+            assert np.all(np.abs(g["samples"]) <= g["amax"])
+            assert np.all(np.abs(g["bulk"]) >= 0.01 * g["amax"]) and max(g["bulk_idx"]) < n3
+
+
 @pytest.mark.parametrize("sphere,nyq", [("octahedron", False), ("icosahedron", False),
                                         ("icosahedron", True)])
 def test_gain_sum_symmetries_of_antipodal_sphere_sets(sphere, nyq):
