@@ -65,6 +65,40 @@ def test_batched_small_mixed_sizes(torch_cuda, precision):
                 assert rel_linf(got[i], ref) <= 1e-11
 
 
+def _check_stored_oracle(insts, items):
+    """Every 32nd instance of the 1024, all its ordered pairs, against the
+    oracle terms stored by tests/golden/make_batched_oracle.py: 32 sampled
+    points and the point of max |Q| within 1e-11 of max |Q|, and two
+    projections of the whole term within 1e-11 max |Q| ||W||_2."""
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(__file__), "golden", "batched_oracle.json")) as fh:
+        gold = json.load(fh)
+    by_item = {(k, p, q): ob for (k, p, q, _, _, ob) in items}
+    checked, worst = 0, 0.0
+    for ks, g in gold["instances"].items():
+        k = int(ks)
+        cfg = insts[k]
+        assert (cfg["N"], cfg["ns"], cfg["Nrho"]) == (g["N"], g["ns"], g["Nrho"])
+        assert abs(cfg["F"].sum() - g["fsum"]) <= 1e-12 * abs(g["fsum"])
+        N = cfg["N"]
+        idx = np.sort(np.random.default_rng(gold["sample_seed"] + N).choice(N ** 3, gold["n_samples"], replace=False))
+        W = np.random.default_rng(gold["proj_seed"] + N).standard_normal((gold["n_proj"], N ** 3))
+        wn = np.linalg.norm(W, axis=1)
+        for key, nodes in g["pairs"].items():
+            p, q = map(int, key.split(","))
+            got = by_item[(k, p, q)].cpu().numpy().reshape(cfg["n_nodes"], -1)
+            for i, r in enumerate(nodes):
+                Q = got[i]
+                e = max(float(np.max(np.abs(Q[idx] - np.asarray(r["samples"])))), abs(Q[r["argmax"]] - r["at_argmax"]))
+                ep = float(np.max(np.abs(W @ Q - np.asarray(r["proj"])) / wn))
+                worst = max(worst, e / r["qmax"], ep / r["qmax"])
+                assert e <= 1e-11 * r["qmax"] and ep <= 1e-11 * r["qmax"], (k, p, q, i)
+                checked += 1
+    assert checked == sum(insts[int(k)]["ns"] ** 2 * insts[int(k)]["n_nodes"] for k in gold["instances"])
+    print("stored oracle: %d instances, %d terms, worst %.3e of max|Q|" % (len(gold["instances"]), checked, worst))
+
+
 @pytest.mark.parametrize("n_inst,precision", [(96, "fp64"), (1024, "fp64"), (1024, "fp32")])
 def test_batched_uneven_instances_N16_24_32(torch_cuda, n_inst, precision):
     """Space-homogeneous instances drawn like the batching workload (N in
@@ -74,13 +108,17 @@ def test_batched_uneven_instances_N16_24_32(torch_cuda, n_inst, precision):
     the 96-instance case 16 instances with N <= 24 (all their ordered
     pairs) and one pair of an N = 32 instance are checked against the
     oracle.  The FP32-mixed plans run the same 1024 instances, also bit for
-    bit against their per-instance launches."""
+    bit against their per-instance launches.  In FP64, every 32nd of the
+    1024 instances (all ordered pairs) is checked against stored oracle
+    terms."""
     torch = torch_cuda
     insts = wl.batched_instances(n_inst=n_inst)
     plans, items, outs_b, outs_s = _run(torch, insts, precision)
     assert len(items) > n_inst
     for ob, os_ in zip(outs_b, outs_s):
         assert torch.equal(ob, os_)
+    if n_inst == 1024 and precision == "fp64":
+        _check_stored_oracle(insts, items)
     if n_inst > 96:
         return
     # sampled instances against the oracle

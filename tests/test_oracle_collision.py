@@ -284,6 +284,27 @@ def test_stored_full_shape_vss_terms_match_this_input():
             assert np.all(np.abs(g["proj"]) <= np.asarray(g["proj_scale"]))
 
 
+def test_stored_batched_terms_match_this_input():
+    """The oracle terms stored by tests/golden/make_batched_oracle.py (every
+    32nd of the 1024 batching instances, all ordered pairs) belong to the
+    instances the seeded workload generator gives here, and are finite with
+    |Q| at the stored argmax equal to the stored max."""
+    import json
+    with open(os.path.join(GOLDEN, "batched_oracle.json")) as fh:
+        gold = json.load(fh)
+    insts = wl.batched_instances(n_inst=1024)
+    assert sorted(int(k) for k in gold["instances"]) == list(range(0, 1024, gold["stride"]))
+    for ks, g in gold["instances"].items():
+        cfg = insts[int(ks)]
+        assert (cfg["N"], cfg["ns"], cfg["Nrho"]) == (g["N"], g["ns"], g["Nrho"])
+        assert abs(cfg["F"].sum() - g["fsum"]) <= 1e-12 * abs(g["fsum"])
+        assert sorted(g["pairs"]) == ["%d,%d" % (p, q) for p in range(cfg["ns"]) for q in range(cfg["ns"])]
+        for nodes in g["pairs"].values():
+            for r in nodes:
+                assert np.all(np.isfinite(r["samples"] + r["proj"])) and abs(r["at_argmax"]) == r["qmax"] > 0
+                assert r["argmax"] < cfg["N"] ** 3 and np.all(np.abs(r["samples"]) <= r["qmax"])
+
+
 def test_stored_couette_step_matches_this_input():
     """The oracle's full Couette SSP-RK3 step stored by
     tests/golden/make_couette_step_oracle.py was computed from the input the
