@@ -12,11 +12,18 @@ dF = F(t + dt) - F(t):
   * four projections sum W_k dF of the whole increment onto seeded normal
     weights, which see an error anywhere.
 
-The step takes 768 collision evaluations (3 stages x 64 nodes x 4 ordered
-pairs), about 10 minutes on 8 host cores.  Only the oracle is called (the
-input comes from the seeded workload generator).
+With --projected it writes couette_step_projected_oracle.json instead: the
+same step with each node's collision term projected onto the conserved
+moments (the FP32-mixed leg of the benchmark), plus the loss scale
+Lambda = max over the stored nodes and species p of sum_q max |loss^{pq}| at
+the initial state, from which the FP32-mixed bar is stated.
 
-    python tests/golden/make_couette_step_oracle.py
+The step takes 768 collision evaluations (3 stages x 64 nodes x 4 ordered
+pairs), about 28 minutes on 8 host cores.
+Only the oracle is called (the input comes from the seeded workload
+generator).
+
+    python tests/golden/make_couette_step_oracle.py [--projected]
 """
 import json
 import os
@@ -30,9 +37,14 @@ NODES = [0, 1, 3, 4, 21, 32, 62, 63]
 
 
 def main():
+    import argparse
     import numpy as np
+    from oracle import conservation as cons
     from oracle import dg as odg
-    from oracle.collide import PairPlan, mixture_collision
+    from oracle.collide import PairPlan, collide_gain_loss, mixture_collision
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--projected", action="store_true")
+    projected = ap.parse_args().projected
     from oracle.quadrature import sphere_set
     from paper_1903_04670_amd import workloads as wl
     cfg = wl.couette_two_species()
@@ -45,10 +57,16 @@ def main():
     prob = odg.Couette1D(cfg["N"], cfg["L"], cfg["masses"], cfg["K"], cfg["P"], cfg["u_left"], cfg["u_right"])
     stage = [0]
 
+    def coll(Y):
+        C = mixture_collision(opl, Y)
+        if projected:
+            C = np.stack([cons.project(C[i], cfg["N"], cfg["L"], cfg["masses"]) for i in range(C.shape[0])])
+        return C
+
     def rhs(X):
         stage[0] += 1
         print("stage %d" % stage[0], flush=True)
-        return prob.rhs(X, lambda Y: mixture_collision(opl, Y))
+        return prob.rhs(X, coll)
     F1 = odg.ssp_rk3(F0, cfg["dt"], rhs)
     dF = F1 - F0
     n3 = cfg["N"] ** 3
@@ -66,13 +84,23 @@ def main():
                             bulk=[float(v) for v in d[bidx]]))
         nodes.append(dict(node=i, species=per))
     W = np.random.default_rng(PROJ_SEED).standard_normal((N_PROJ, dF.size))
-    doc = dict(workload=cfg["name"], dt=cfg["dt"], projection=False, sample_seed=SAMPLE_SEED,
+    lam = None
+    if projected:
+        lam = 0.0
+        # over the stored nodes (the nodes' inputs differ by 1% noise, and a
+        # smaller scale only tightens the bar)
+        for i in NODES:
+            for p in range(ns):
+                lam = max(lam, sum(float(np.max(np.abs(collide_gain_loss(opl[p][q], F0[i, p], F0[i, q])[1])))
+                                   for q in range(ns)))
+    doc = dict(workload=cfg["name"], dt=cfg["dt"], projection=projected, loss_scale=lam, sample_seed=SAMPLE_SEED,
                proj_seed=PROJ_SEED, n_proj=N_PROJ, sample_idx=[int(v) for v in idx],
                inputs=dict(shape=list(F0.shape), total=float(F0.sum()),
                            sums=[[float(F0[i, p].sum()) for p in range(ns)] for i in NODES]),
                dmax=float(np.max(np.abs(dF))), proj=[float(v) for v in W @ dF.ravel()],
                nodes=nodes)
-    with open(os.path.join(HERE, "couette_step_oracle.json"), "w") as fh:
+    name = "couette_step_projected_oracle.json" if projected else "couette_step_oracle.json"
+    with open(os.path.join(HERE, name), "w") as fh:
         json.dump(doc, fh, indent=0)
         fh.write("\n")
     print("written; max |dF| %.6e" % doc["dmax"])

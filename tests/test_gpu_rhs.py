@@ -180,21 +180,17 @@ def test_couette_full_size_rhs_sampled_nodes(torch_cuda):
     assert np.isfinite(got).all()
 
 
-def test_couette_full_size_ssp_rk3_step_against_stored_oracle(torch_cuda):
-    """One SSP-RK3 step (dt = 1e-3) of the benchmark's workload at full size
-    (64 nodes, two species, N = 32, M = 12, N_rho = 16, K = 16, P = 3) as the
-    benchmark runs it (a captured graph, then replayed on the same state
-    array), against the oracle's step stored by
-    tests/golden/make_couette_step_oracle.py: the increment dF at sampled,
-    bulk and peak points of eight nodes (both walls, element boundaries)
-    within 1e-11 of max |dF|, and four projections of the whole increment
-    within 1e-11 max |dF| ||W||_2."""
+def _full_step_against_stored(torch, name, precision, project, bar_of):
+    """One SSP-RK3 step of the full Couette workload, first through the
+    captured graph and then through its replay on the same state array,
+    against a step stored by tests/golden/make_couette_step_oracle.py; returns
+    the worst point and projection errors.  bar_of(gold) gives the bar."""
     import json
     import os
     from paper_1903_04670_amd import dgfs
-    torch = torch_cuda
-    with open(os.path.join(os.path.dirname(__file__), "golden", "couette_step_oracle.json")) as fh:
+    with open(os.path.join(os.path.dirname(__file__), "golden", name)) as fh:
         gold = json.load(fh)
+    assert gold["projection"] == project
     cfg = wl.couette_two_species()
     F0 = cfg["F"]
     # the seeded input must be the one the stored step was computed from
@@ -204,17 +200,17 @@ def test_couette_full_size_ssp_rk3_step_against_stored_oracle(torch_cuda):
         for p in range(cfg["ns"]):
             ref = gold["inputs"]["sums"][k][p]
             assert abs(F0[nd["node"], p].sum() - ref) <= 1e-12 * abs(ref)
-    pl = gpu_plan(cfg, dg_order=cfg["P"])
+    pl = gpu_plan(cfg, precision=precision, dg_order=cfg["P"])
     mesh = dgfs.make_mesh(cfg["K"])
     ws = dgfs.workspace(pl, cfg["n_nodes"], dgfs.OP_STEP)
     F = torch.from_numpy(F0).cuda()
     W = np.random.default_rng(gold["proj_seed"]).standard_normal((gold["n_proj"], F0.size))
     wn = np.linalg.norm(W, axis=1)
     idx = np.asarray(gold["sample_idx"])
-    bar = TOL * gold["dmax"]
+    bar = bar_of(gold)
     for rep in range(2):  # the first call captures the step's graph, the second replays it
         F.copy_(torch.from_numpy(F0))
-        dgfs.step(pl, F, gold["dt"], 1, mesh=mesh, ws=ws)
+        dgfs.step(pl, F, gold["dt"], 1, mesh=mesh, project=project, ws=ws)
         torch.cuda.synchronize()
         dF = F.cpu().numpy() - F0
         e_proj = float(np.max(np.abs(W @ dF.ravel() - np.asarray(gold["proj"])) / wn))
@@ -225,8 +221,33 @@ def test_couette_full_size_ssp_rk3_step_against_stored_oracle(torch_cuda):
                 e_pt = max(e_pt, float(np.max(np.abs(d[idx] - np.asarray(g["samples"])))),
                            float(np.max(np.abs(d[np.asarray(g["bulk_idx"])] - np.asarray(g["bulk"])))),
                            abs(d[g["argmax"]] - g["at_argmax"]))
-        print("step call %d: points %.3e, projections %.3e of max|dF|" % (rep, e_pt / gold["dmax"], e_proj / gold["dmax"]))
+        print("%s step call %d: points %.3e, projections %.3e of max|dF|; %.3e, %.3e of the bar"
+              % (precision, rep, e_pt / gold["dmax"], e_proj / gold["dmax"], e_pt / bar, e_proj / bar))
         assert e_pt <= bar and e_proj <= bar, rep
+
+
+def test_couette_full_size_ssp_rk3_step_against_stored_oracle(torch_cuda):
+    """One SSP-RK3 step (dt = 1e-3) of the benchmark's workload at full size
+    (64 nodes, two species, N = 32, M = 12, N_rho = 16, K = 16, P = 3) as the
+    benchmark runs it (a captured graph, then replayed on the same state
+    array), against the oracle's step stored by
+    tests/golden/make_couette_step_oracle.py: the increment dF at sampled,
+    bulk and peak points of eight nodes (both walls, element boundaries)
+    within 1e-11 of max |dF|, and four projections of the whole increment
+    within 1e-11 max |dF| ||W||_2."""
+    _full_step_against_stored(torch_cuda, "couette_step_oracle.json", "fp64", False,
+                              lambda gold: TOL * gold["dmax"])
+
+
+def test_couette_full_size_fp32_mixed_projected_step_against_stored_oracle(torch_cuda):
+    """The benchmark's FP32-mixed leg: the same full-size step with FP32
+    transforms and the FP64 projection of each node's collision term, against
+    the oracle's projected step.  Bar dt x 4e-6 x Lambda, where Lambda is
+    the largest sum over partners q of max |loss^{pq}| of a species at the
+    initial state: twice the per-evaluation FP32-mixed bound (2e-6 of the
+    loss term), for the projection and the three stages."""
+    _full_step_against_stored(torch_cuda, "couette_step_projected_oracle.json", "fp32", True,
+                              lambda gold: gold["dt"] * 4e-6 * gold["loss_scale"])
 
 
 def test_projected_rhs_conserves(torch_cuda):

@@ -305,15 +305,20 @@ def test_stored_batched_terms_match_this_input():
                 assert r["argmax"] < cfg["N"] ** 3 and np.all(np.abs(r["samples"]) <= r["qmax"])
 
 
-def test_stored_couette_step_matches_this_input():
-    """The oracle's full Couette SSP-RK3 step stored by
-    tests/golden/make_couette_step_oracle.py was computed from the input the
-    seeded workload generator gives here, and is self-consistent: finite,
+@pytest.mark.parametrize("name,projected", [("couette_step_oracle.json", False),
+                                            ("couette_step_projected_oracle.json", True)])
+def test_stored_couette_step_matches_this_input(name, projected):
+    """The oracle's full Couette SSP-RK3 steps stored by
+    tests/golden/make_couette_step_oracle.py (plain, and with the projected
+    collision term and its loss scale) were computed from the input the
+    seeded workload generator gives here, and are self-consistent: finite,
     each stored peak equal to its array's max and at most the global max,
     bulk points at >= 1% of their peak."""
     import json
-    with open(os.path.join(GOLDEN, "couette_step_oracle.json")) as fh:
+    with open(os.path.join(GOLDEN, name)) as fh:
         gold = json.load(fh)
+    assert gold["projection"] == projected
+    assert (gold["loss_scale"] > 0) if projected else gold["loss_scale"] is None
     cfg = wl.couette_two_species()
     F = cfg["F"]
     assert list(F.shape) == gold["inputs"]["shape"] and gold["dt"] == cfg["dt"]
