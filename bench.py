@@ -599,7 +599,7 @@ def main():
                     "kernels changed since the counters were taken",
             "fp64": path["fp64"], "fp32_mixed": path["fp32"]},
         "model_equivalent": {
-            "what": "not a roofline fraction: the HBM rate the survey's cost model (one HBM round trip of an "
+            "what": "not a roofline fraction: the HBM rate a per-term cost model (one HBM round trip of an "
                     "N^3 complex intermediate per (r, m) term plus three real N^3 arrays) would need for the "
                     "measured evals/s; this design moves fewer bytes (sum over m before the forward transform, "
                     "shared x-shifted arrays, reused gain sums), see path_hbm",
