@@ -180,7 +180,7 @@ def test_couette_full_size_rhs_sampled_nodes(torch_cuda):
     assert np.isfinite(got).all()
 
 
-def _full_step_against_stored(torch, name, precision, project, bar_of):
+def _full_step_against_stored(torch, name, precision, project, bar_of, nyquist_zero=False):
     """One SSP-RK3 step of the full Couette workload, first through the
     captured graph and then through its replay on the same state array,
     against a step stored by tests/golden/make_couette_step_oracle.py; returns
@@ -190,7 +190,7 @@ def _full_step_against_stored(torch, name, precision, project, bar_of):
     from paper_1903_04670_amd import dgfs
     with open(os.path.join(os.path.dirname(__file__), "golden", name)) as fh:
         gold = json.load(fh)
-    assert gold["projection"] == project
+    assert gold["projection"] == project and gold.get("nyquist_zero", False) == nyquist_zero
     cfg = wl.couette_two_species()
     F0 = cfg["F"]
     # the seeded input must be the one the stored step was computed from
@@ -200,7 +200,7 @@ def _full_step_against_stored(torch, name, precision, project, bar_of):
         for p in range(cfg["ns"]):
             ref = gold["inputs"]["sums"][k][p]
             assert abs(F0[nd["node"], p].sum() - ref) <= 1e-12 * abs(ref)
-    pl = gpu_plan(cfg, precision=precision, dg_order=cfg["P"])
+    pl = gpu_plan(cfg, precision=precision, dg_order=cfg["P"], nyquist_zero=nyquist_zero)
     mesh = dgfs.make_mesh(cfg["K"])
     ws = dgfs.workspace(pl, cfg["n_nodes"], dgfs.OP_STEP)
     F = torch.from_numpy(F0).cuda()
@@ -237,6 +237,15 @@ def test_couette_full_size_ssp_rk3_step_against_stored_oracle(torch_cuda):
     within 1e-11 max |dF| ||W||_2."""
     _full_step_against_stored(torch_cuda, "couette_step_oracle.json", "fp64", False,
                               lambda gold: TOL * gold["dmax"])
+
+
+def test_couette_full_size_nyquist_zero_step_against_stored_oracle(torch_cuda):
+    """The Nyquist-zeroed variant (plan option nyquist_zero: the real-packed
+    gain kernel and half-spectrum x-shifted arrays) on the same full-size
+    step, captured and replayed, against the oracle's step under that
+    variant; bar 1e-11 of max |dF|, as for the plain step."""
+    _full_step_against_stored(torch_cuda, "couette_step_nyquist_oracle.json", "fp64", False,
+                              lambda gold: TOL * gold["dmax"], nyquist_zero=True)
 
 
 def test_couette_full_size_fp32_mixed_projected_step_against_stored_oracle(torch_cuda):

@@ -306,7 +306,8 @@ def test_stored_batched_terms_match_this_input():
 
 
 @pytest.mark.parametrize("name,projected", [("couette_step_oracle.json", False),
-                                            ("couette_step_projected_oracle.json", True)])
+                                            ("couette_step_projected_oracle.json", True),
+                                            ("couette_step_nyquist_oracle.json", False)])
 def test_stored_couette_step_matches_this_input(name, projected):
     """The oracle's full Couette SSP-RK3 steps stored by
     tests/golden/make_couette_step_oracle.py (plain, and with the projected
